@@ -1,0 +1,183 @@
+"""Seeded synthetic inputs shared by the oracle-side tests and the GPU path.
+
+This module holds no arithmetic of the method: it only builds parameter dicts
+and initial macroscopic fields (density, velocity, temperature) from closed
+forms and a SplitMix64 stream.  Both the oracle and the GPU library receive the
+same arrays and turn them into f = f^eq themselves.
+
+Workloads (lattice units: ds = 1/N, m = k_B = 1):
+  shear32     32x32 periodic shear wave, a = 9/49, b = 2/21 (T_c = 4/7), T = 1,
+              n = 1, u_y = 1e-3 sin(2 pi x), tau = 0.01, dt = 5e-4, ds = 1/32.
+  wave2048    2048x2048 periodic, superposed shear (u_y amplitude 1e-3) and
+              longitudinal (n amplitude 1e-3) waves along x, wavelength 64
+              cells (ds = 1/64), tau = 0.005, dt = 5e-4, T = 1.
+  wave64      the 64x64 crop of wave2048 (one wavelength; the 2048 run is this
+              one tiled 32x32 times).
+  spinodal    periodic spinodal decomposition at T = 0.9 T_c, n = 3.5 (1 +
+              0.01 (2U - 1)), u = 0, ds = 1/320, dt = 2e-4, tau = 0.005.
+  channel     periodic in x, diffuse walls at y = -ds/2 and (ny - 1/2) ds with
+              wall temperature T_w, fluid initially at T_c with n = 3.5 (1 +
+              0.005 (2U - 1)) (the cooled-plates quench of Sec. 7).
+  channels    256 channels with seeded sizes and wall temperatures.
+U is uniform on [0, 1): the top 53 bits of successive SplitMix64 outputs,
+drawn in row-major order (y outer, x inner).  Cell centres are
+x_i = (i + 1/2) ds, 0-based.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+VDW_A = 9.0 / 49.0
+VDW_B = 2.0 / 21.0
+T_CRIT = 4.0 / 7.0     # critical temperature 8a/(27b) of the EOS above
+N_CRIT = 3.5           # critical density 1/(3b)
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, count: int) -> np.ndarray:
+    """``count`` successive SplitMix64 outputs (Steele, Lea, Flood 2014)."""
+    out = np.empty(count, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        state = np.uint64(seed & _M64)
+        # vectorised: state_i = seed + (i+1) * golden
+        inc = np.uint64(0x9E3779B97F4A7C15)
+        z = state + inc * np.arange(1, count + 1, dtype=np.uint64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    out[:] = z
+    return out
+
+
+def uniform(seed: int, count: int) -> np.ndarray:
+    """Uniform doubles on [0, 1) from the top 53 bits of SplitMix64."""
+    z = splitmix64(seed, count)
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+@dataclass
+class Case:
+    name: str
+    params: dict
+    n: np.ndarray
+    ux: np.ndarray
+    uy: np.ndarray
+    T: np.ndarray
+    steps: int
+    note: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def fields(self):
+        return self.n, self.ux, self.uy, self.T
+
+
+def _params(nx, ny, ds, dt, tau, a=VDW_A, b=VDW_B, sigma=1e-4, bc_y=0,
+            tw=1.0, uw=0.0, precision=0, rho_ref=1.0):
+    return dict(nx=int(nx), ny=int(ny), ds=float(ds), dt=float(dt), tau=float(tau),
+                a=float(a), b=float(b), sigma=float(sigma), bc_x=0, bc_y=int(bc_y),
+                tw_lo=float(tw), tw_hi=float(tw), uw_lo=float(uw), uw_hi=float(uw),
+                precision=int(precision), rho_ref=float(rho_ref))
+
+
+def _xc(nx, ds):
+    return (np.arange(nx) + 0.5) * ds
+
+
+def shear32(nx=32, ny=32, steps=100, **kw):
+    ds = 1.0 / nx
+    x = _xc(nx, ds)
+    n = np.ones((ny, nx))
+    ux = np.zeros((ny, nx))
+    uy = np.broadcast_to(1e-3 * np.sin(2 * np.pi * x), (ny, nx)).copy()
+    T = np.ones((ny, nx))
+    p = _params(nx, ny, ds, 5e-4, 0.01, **kw)
+    return Case("shear32", p, n, ux, uy, T, steps)
+
+
+def wave(nx=2048, ny=2048, cells_per_wavelength=64, steps=1000, **kw):
+    ds = 1.0 / cells_per_wavelength
+    x = _xc(nx, ds)
+    n = np.broadcast_to(1.0 + 1e-3 * np.cos(2 * np.pi * x), (ny, nx)).copy()
+    ux = np.zeros((ny, nx))
+    uy = np.broadcast_to(1e-3 * np.sin(2 * np.pi * x), (ny, nx)).copy()
+    T = np.ones((ny, nx))
+    p = _params(nx, ny, ds, 5e-4, 0.005, **kw)
+    return Case(f"wave{nx}x{ny}", p, n, ux, uy, T, steps)
+
+
+def wave2048(**kw):
+    return wave(2048, 2048, **kw)
+
+
+def wave64(**kw):
+    return wave(64, 64, **kw)
+
+
+def spinodal(nx=4096, ny=4096, seed=3, steps=5000, ds=1.0 / 320, dt=2e-4, tau=0.005,
+             temperature=0.9 * T_CRIT, noise=0.01, **kw):
+    U = uniform(seed, nx * ny).reshape(ny, nx)
+    n = N_CRIT * (1.0 + noise * (2.0 * U - 1.0))
+    ux = np.zeros((ny, nx))
+    uy = np.zeros((ny, nx))
+    T = np.full((ny, nx), float(temperature))
+    p = _params(nx, ny, ds, dt, tau, **kw)
+    return Case(f"spinodal{nx}x{ny}", p, n, ux, uy, T, steps)
+
+
+def channel(nx=64, ny=128, seed=4, steps=2000, tw=0.8 * T_CRIT, ds=1.0 / 320, dt=2e-4,
+            tau=0.005, noise=0.005, t0=T_CRIT, **kw):
+    U = uniform(seed, nx * ny).reshape(ny, nx)
+    n = N_CRIT * (1.0 + noise * (2.0 * U - 1.0))
+    ux = np.zeros((ny, nx))
+    uy = np.zeros((ny, nx))
+    T = np.full((ny, nx), float(t0))
+    p = _params(nx, ny, ds, dt, tau, bc_y=1, tw=tw, **kw)
+    return Case(f"channel{nx}x{ny}", p, n, ux, uy, T, steps)
+
+
+def channels(count=256, seed=4, nx_range=(64, 512), ny_range=(128, 1024),
+             tw_range=(0.7, 0.95), steps=2000, precision=1, **kw):
+    """``count`` walled channels.  One SplitMix64 stream (seed) is consumed in
+    the order: per channel nx, ny, T_w; then the noise of every channel, channel
+    by channel, row-major."""
+    head = uniform(seed, 3 * count).reshape(count, 3)
+    lo_x, hi_x = nx_range
+    lo_y, hi_y = ny_range
+    sizes = []
+    for c in range(count):
+        nx = lo_x + int(head[c, 0] * (hi_x - lo_x + 1))
+        ny = lo_y + int(head[c, 1] * (hi_y - lo_y + 1))
+        tw = (tw_range[0] + (tw_range[1] - tw_range[0]) * head[c, 2]) * T_CRIT
+        sizes.append((nx, ny, tw))
+    total = sum(nx * ny for nx, ny, _ in sizes)
+    noise = uniform(seed, 3 * count + total)[3 * count:]
+    cases = []
+    off = 0
+    for c, (nx, ny, tw) in enumerate(sizes):
+        U = noise[off:off + nx * ny].reshape(ny, nx)
+        off += nx * ny
+        n = N_CRIT * (1.0 + 0.005 * (2.0 * U - 1.0))
+        z = np.zeros((ny, nx))
+        p = _params(nx, ny, 1.0 / 320, 2e-4, 0.005, bc_y=1, tw=tw, precision=precision,
+                    rho_ref=N_CRIT, **kw)
+        cases.append(Case(f"channel[{c}]{nx}x{ny}", p, n, z, z.copy(),
+                          np.full((ny, nx), T_CRIT), steps))
+    return cases
+
+
+def tile(case: Case, rx: int, ry: int) -> Case:
+    """The same workload repeated rx times along x and ry times along y."""
+    p = dict(case.params)
+    p["nx"] = case.params["nx"] * rx
+    p["ny"] = case.params["ny"] * ry
+    t = lambda a: np.tile(a, (ry, rx))
+    return Case(case.name + f"x{rx}x{ry}", p, t(case.n), t(case.ux), t(case.uy), t(case.T),
+                case.steps)
+
+
+def random_f_perturbation(seed: int, shape, amplitude: float) -> np.ndarray:
+    """Seeded multiplicative noise (1 + amplitude (2U - 1)) for raw f tests."""
+    U = uniform(seed, int(np.prod(shape))).reshape(shape)
+    return 1.0 + amplitude * (2.0 * U - 1.0)

@@ -1,0 +1,143 @@
+/*
+ * olb.h -- C-ABI of the MI355X (gfx950) D2Q25 off-lattice thermal Boltzmann
+ * library: the per-stage update of the 25 distributions of the Gauss-Hermite
+ * Q = 5 model of Busuioc, Ambrus, Biciusca and Sofonea (arXiv:1702.01690)
+ * under third-order TVD Runge-Kutta.
+ *
+ * Conventions
+ *   - Lattice nx * ny, node (x, y) at ((x + 1/2) ds, (y + 1/2) ds), 0-based.
+ *   - Population index k = 5 * ky + kx; kx, ky = 0..4 index the ascending roots
+ *     of He_5 (Table trots): p = (R[kx], R[ky]), R[2] = 0.
+ *   - Host macroscopic arrays are double [ny][nx]; host distributions are
+ *     double [25][ny][nx].
+ *   - Units of Sec. 2.1 with m = k_B = 1.
+ *
+ * Ownership
+ *   - The caller owns all host arrays; they are read or written synchronously
+ *     inside the call and may be reused on return.
+ *   - The caller owns device memory: olb_init receives a device workspace of at
+ *     least olb_workspace_bytes() bytes (256-byte aligned) and a hipStream_t.
+ *     The library never allocates device memory; the workspace and stream must
+ *     outlive the context.  All device work is enqueued on that stream.
+ *   - One context may be used by one host thread at a time.  Separate contexts
+ *     are independent.
+ *
+ * Errors
+ *   Every call returns an olb_status (0 = OLB_OK, negative = error).  No C++
+ *   exception crosses this boundary.  After an error, olb_last_error() holds
+ *   a human-readable message for that context.
+ */
+#ifndef OLB_H
+#define OLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct olb_ctx olb_ctx;
+
+typedef enum {
+  OLB_OK = 0,
+  OLB_E_ARG = -1,        /* null pointer, bad size, unsupported kind            */
+  OLB_E_CFL = -2,        /* p_max dt / (m ds) >= 1 (CFL condition, Sec. 4.1)    */
+  OLB_E_DOMAIN = -3,     /* n outside (0, 1/b), T <= 0, tau <= 0, T_w <= 0      */
+  OLB_E_NONFINITE = -4,  /* a distribution became NaN or infinite during a step */
+  OLB_E_WORKSPACE = -5,  /* workspace too small or misaligned                   */
+  OLB_E_DEVICE = -6,     /* a HIP runtime call failed                           */
+  OLB_E_STATE = -7       /* call out of order (e.g. step before set_fields)     */
+} olb_status;
+
+enum { OLB_BC_PERIODIC = 0, OLB_BC_DIFFUSE = 1 };
+enum { OLB_FP64 = 0, OLB_FP32_MIXED = 1 };
+
+/* Problem statement of Secs. 2 and 3 of the paper:
+ *   nx, ny      lattice nodes (frak N_1 x frak N_2).
+ *   ds, dt      lattice spacing and RK-3 time step (Eq. rk3).
+ *   tau         BGK relaxation time (Eq. evolution), > 0.
+ *   a, b        van der Waals EOS p^w = nT/(1 - bn) - a n^2 (Eq. vdw is
+ *               a = 9/8, b = 1/3).
+ *   sigma       surface-tension parameter of Eq. F_def, >= 0.
+ *   bc_x, bc_y  per-axis boundary kind: both ends periodic, or diffuse-
+ *               reflection walls (Sec. 3.4.2).  Walls are supported across y
+ *               only (bc_x must be periodic); the paper's walls across x map to
+ *               this case by exchanging the axes.  Walls need ny >= 3.
+ *   tw_lo/hi    wall temperature at y = -ds/2 / y = (ny - 1/2) ds.
+ *   uw_lo/hi    tangential (x) wall velocity at the same walls.
+ *   precision   OLB_FP64: FP64 storage and arithmetic throughout.
+ *               OLB_FP32_MIXED: f stored in FP32 as f - w_k rho_ref; moment
+ *               sums, the vdW pressure and the 49-point stencils in FP64; WENO,
+ *               force term, collision and RK combine in FP32.
+ *   rho_ref     reference density of the FP32 departure storage. */
+typedef struct olb_params {
+  int32_t nx, ny;
+  double ds, dt, tau;
+  double a, b, sigma;
+  int32_t bc_x, bc_y;
+  double tw_lo, tw_hi, uw_lo, uw_hi;
+  int32_t precision;
+  double rho_ref;
+} olb_params;
+
+/* Device workspace size for one context with these parameters. */
+olb_status olb_workspace_bytes(const olb_params* p, size_t* bytes);
+
+/* Validate p (CFL, tau > 0, sizes, kinds), carve the caller's workspace and
+ * bind the stream (hipStream_t passed as void*; NULL = default stream). */
+olb_status olb_init(const olb_params* p, void* dev_workspace, size_t bytes,
+                    void* hip_stream, olb_ctx** out);
+
+/* f <- f^eq(n, u, T) (Eqs. feq, g_alpha) from host fields [ny][nx]; checks
+ * n in (0, 1/b), T > 0 and finiteness.  Synchronous. */
+olb_status olb_set_fields(olb_ctx* c, const double* n, const double* ux,
+                          const double* uy, const double* T);
+
+/* Advance nsteps full RK-3 steps (Eq. rk3), each of three stages computing
+ * L[f] of Eq. ecast: moments, EOS, 49-point force, force term of Eq. derf,
+ * Hermite equilibrium, BGK, WENO-5 fluxes in x and y, wall ghosts
+ * (Secs. 2.2-3.4).  Asynchronous on the context's stream: it only enqueues
+ * kernels.  A non-finite density produced by a step sets a device flag that
+ * the next synchronising call (olb_sync, olb_moments, olb_get_f) reports as
+ * OLB_E_NONFINITE; f is left as computed. */
+olb_status olb_step(olb_ctx* c, int32_t nsteps);
+
+/* Wait for the context's stream; OLB_E_NONFINITE if any step since the last
+ * olb_set_fields / olb_set_f produced a non-finite density. */
+olb_status olb_sync(olb_ctx* c);
+
+/* n, u_x, u_y, T of the current f into host arrays [ny][nx] (FP64), from the
+ * moments of Sec. 2.2 (T = sum f |p - u|^2 / (2 n), D = 2).  Synchronises
+ * the stream; reports OLB_E_NONFINITE like olb_sync (outputs are filled). */
+olb_status olb_moments(olb_ctx* c, double* n, double* ux, double* uy, double* T);
+
+/* Same moments into a caller-owned device buffer of 4 * nx * ny doubles
+ * (n, then u_x, u_y, T planes).  Asynchronous. */
+olb_status olb_moments_device(olb_ctx* c, double* dev_out);
+
+/* Snapshot / restore of the full distribution, host double [25][ny][nx].
+ * FP32_MIXED contexts convert on the fly.  Synchronous. */
+olb_status olb_get_f(olb_ctx* c, double* f);
+olb_status olb_set_f(olb_ctx* c, const double* f);
+
+/* Wall densities n_w of the last stage (Eq. nw), host double [nx] each;
+ * OLB_E_STATE without walls.  Synchronous. */
+olb_status olb_wall_density(olb_ctx* c, double* nw_lo, double* nw_hi);
+
+/* Block height of the stage kernel: 16 (default) or 8 waves per workgroup;
+ * each workgroup updates 63 x (by - 1) nodes.  Results do not depend on it. */
+olb_status olb_set_tile(olb_ctx* c, int32_t by);
+
+/* Number of stage-kernel launches olb_step enqueues per RK-3 step (3), and
+ * of wall-ghost launches (3 with walls, else 0). */
+olb_status olb_launch_counts(const olb_ctx* c, int32_t* stage, int32_t* walls);
+
+const char* olb_last_error(const olb_ctx* c);
+const char* olb_strerror(olb_status s);
+void olb_free(olb_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

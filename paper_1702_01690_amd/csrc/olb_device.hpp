@@ -1,0 +1,62 @@
+// olb_device.hpp -- launch interface between the host runtime and the gfx950
+// kernels of the D2Q25 stage update.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace olbk {
+
+// Storage of one distribution array: 25 planes, each (ny + 6) rows of nx
+// values (3 ghost rows below and above the lattice for diffuse walls), x
+// fastest.  Interior row y lives at plane row y + 3.
+struct Geometry {
+  int nx, ny;
+  int64_t ps;      // plane stride in elements: (ny + 6) * nx
+  int walls;       // 1: diffuse walls across y, 0: periodic y
+};
+
+struct StageArgs {
+  Geometry g;
+  const void* fsrc;     // f^(s-1)
+  const void* fn;       // f^n (RK base); unused when A == 0
+  void* fdst;           // f^(s)
+  const double* cin;    // carried n and Delta p of fsrc: [2][ny][nx]
+  double* cout;         // carried n and Delta p of fdst
+  int* flag;            // set to 1 when a non-finite density is produced
+  double inv_ds, inv_ds3, dt, inv_tau, a, b, sigma;
+  double A, B;          // f_dst = A f^n + B (f_src + dt L[f_src])
+  double rho0;          // FP32 departure base (f = w_k rho0 + stored value)
+  int tiles_x, ntiles;
+};
+
+struct WallArgs {
+  Geometry g;
+  void* f;              // the stage's source array; ghost rows are written
+  double* nw;           // [2][nx] wall densities (lower, upper)
+  double tw[2], uw[2];  // lower / upper wall temperature and tangential velocity
+  double rho0;
+};
+
+// Tile geometry of the stage kernel: 64 lanes across x produce 63 cells, BY
+// waves across y produce BY - 1 rows.
+constexpr int TILE_X = 63;
+
+hipError_t launch_stage(const StageArgs& a, int real_bytes, int by, hipStream_t s);
+hipError_t launch_walls(const WallArgs& a, int real_bytes, hipStream_t s);
+// f = f^eq(n, u, T) from device fields [4][ny][nx]; also writes the carry.
+hipError_t launch_init(const Geometry& g, const double* fields, void* f, double* carry,
+                       double rho0, double a, double b, int real_bytes, hipStream_t s);
+// n, u_x, u_y, T planes [4][ny][nx] of f.
+hipError_t launch_moments(const Geometry& g, const void* f, double* out, double rho0,
+                          int real_bytes, hipStream_t s);
+// carried n and Delta p of f.
+hipError_t launch_carry(const Geometry& g, const void* f, double* carry, double rho0,
+                        double a, double b, int real_bytes, hipStream_t s);
+// packed double [25][ny][nx] <-> stored array.
+hipError_t launch_pack(const Geometry& g, const void* f, double* out, double rho0,
+                       int real_bytes, hipStream_t s);
+hipError_t launch_unpack(const Geometry& g, const double* in, void* f, double rho0,
+                         int real_bytes, hipStream_t s);
+
+}  // namespace olbk

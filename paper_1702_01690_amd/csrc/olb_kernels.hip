@@ -1,0 +1,737 @@
+// olb_kernels.hip -- gfx950 kernels of the D2Q25 off-lattice thermal Boltzmann
+// stage update (arXiv:1702.01690, Secs. 2-3).
+//
+// stage_kernel  one RK-3 stage, fused: moments, EOS, 49-point force, Hermite
+//               equilibrium, force term, BGK, WENO-5 fluxes in x and y and the
+//               RK combine, plus the carried (n, Delta p) of the result for the
+//               next stage's stencils.
+// walls_kernel  diffuse-reflection ghost rows of the stage's source array.
+// init / moments / carry / pack / unpack  set-up and read-out.
+//
+// Data layout: f[k][y + 3][x] (see Geometry), one cell per thread.  A 64 x BY
+// thread block covers 64 x BY nodes; lane 63 and wave BY - 1 only provide the
+// face fluxes of their neighbours, so each block writes 63 x (BY - 1) cells.
+// Per population, the tile plus a 3-node halo (69 x (BY + 5) values) is staged
+// in LDS; each thread reconstructs the WENO value on its left (x) and lower (y)
+// face only, the right face arrives from lane + 1 by a cross-lane shuffle and
+// the upper face from the next wave through LDS.
+#include <type_traits>
+
+#include "olb_consts.hpp"
+#include "olb_device.hpp"
+
+namespace olbk {
+using namespace olbc;
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// Reciprocal: hardware estimate refined by two Newton steps (FP64), or the
+// single-precision estimate (FP32).
+__device__ __forceinline__ double frcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float frcp(float d) { return __builtin_amdgcn_rcpf(d); }
+
+// WENO-5 reconstruction at i + 1/2 for a positive speed from
+// (f_{i-2}, f_{i-1}, f_i, f_{i+1}, f_{i+2}) (Eqs. weno5_flux..weno5_sigma).
+// No epsilon: when indicators vanish, the weights follow Tab. weno, i.e. the
+// ideal weights restricted to the vanishing candidates.  Indicators are formed
+// from first differences, so a vanishing indicator is exactly "three equal
+// values".  The weights use a single reciprocal:
+//   w_q ~ delta_q prod_{r != q} s_r^2.
+__device__ __forceinline__ double weno_rec(double v0, double v1, double v2, double v3, double v4) {
+  const double d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
+  const double a1 = d2 - d1, b1 = 3.0 * d2 - d1;
+  const double a2 = d3 - d2, b2 = d2 + d3;
+  const double a3 = d4 - d3, b3 = 3.0 * d3 - d4;
+  const double s1 = (13.0 / 12.0) * a1 * a1 + 0.25 * b1 * b1;
+  const double s2 = (13.0 / 12.0) * a2 * a2 + 0.25 * b2 * b2;
+  const double s3 = (13.0 / 12.0) * a3 * a3 + 0.25 * b3 * b3;
+  const double q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
+  double w1 = D1 * q2 * q3, w2 = D2 * q1 * q3, w3 = D3 * q1 * q2;
+  const bool z1 = s1 == 0.0, z2 = s2 == 0.0, z3 = s3 == 0.0;
+  if (z1 | z2 | z3) {
+    w1 = z1 ? D1 : 0.0;
+    w2 = z2 ? D2 : 0.0;
+    w3 = z3 ? D3 : 0.0;
+  }
+  // candidate values minus f_i
+  const double e1 = (5.0 / 6.0) * d2 - (1.0 / 3.0) * d1;
+  const double e2 = (1.0 / 6.0) * d2 + (1.0 / 3.0) * d3;
+  const double e3 = (2.0 / 3.0) * d3 - (1.0 / 6.0) * d4;
+  return v2 + (w1 * e1 + w2 * e2 + w3 * e3) * frcp(w1 + w2 + w3);
+}
+
+// FP32 variant: the weights are invariant under scaling of f, so the first
+// differences are normalised by their largest magnitude before squaring; this
+// keeps s^4 products inside the single-precision range.  A product that still
+// underflows is treated as a vanishing indicator.
+__device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3, float v4) {
+  float d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
+  const float m = fmaxf(fmaxf(fabsf(d1), fabsf(d2)), fmaxf(fabsf(d3), fabsf(d4)));
+  const float im = m > 0.0f ? frcp(m) : 0.0f;
+  d1 *= im; d2 *= im; d3 *= im; d4 *= im;
+  const float a1 = d2 - d1, b1 = 3.0f * d2 - d1;
+  const float a2 = d3 - d2, b2 = d2 + d3;
+  const float a3 = d4 - d3, b3 = 3.0f * d3 - d4;
+  const float s1 = (13.0f / 12.0f) * a1 * a1 + 0.25f * b1 * b1;
+  const float s2 = (13.0f / 12.0f) * a2 * a2 + 0.25f * b2 * b2;
+  const float s3 = (13.0f / 12.0f) * a3 * a3 + 0.25f * b3 * b3;
+  const float q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
+  float w1 = 0.1f * q2 * q3, w2 = 0.6f * q1 * q3, w3 = 0.3f * q1 * q2;
+  const bool z1 = q1 == 0.0f, z2 = q2 == 0.0f, z3 = q3 == 0.0f;
+  if (z1 | z2 | z3) {
+    w1 = z1 ? 0.1f : 0.0f;
+    w2 = z2 ? 0.6f : 0.0f;
+    w3 = z3 ? 0.3f : 0.0f;
+  }
+  const float e1 = (5.0f / 6.0f) * d2 - (1.0f / 3.0f) * d1;
+  const float e2 = (1.0f / 6.0f) * d2 + (1.0f / 3.0f) * d3;
+  const float e3 = (2.0f / 3.0f) * d3 - (1.0f / 6.0f) * d4;
+  return v2 + m * ((w1 * e1 + w2 * e2 + w3 * e3) * frcp(w1 + w2 + w3));
+}
+
+// Moment sums of one node: n = sum f, j = sum p f, e = sum |p|^2 f.  With the
+// FP32 departure storage f = w_k rho0 + stored, and sum w = 1, sum w p = 0,
+// sum w |p|^2 = 2.
+template <typename Real>
+__device__ __forceinline__ void sums25(const Real* f, double rho0, double& n, double& jx,
+                                       double& jy, double& e) {
+  double cs[5], rs[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    cs[i] = 0.0;
+    rs[i] = 0.0;
+  }
+#pragma unroll
+  for (int ky = 0; ky < 5; ++ky)
+#pragma unroll
+    for (int kx = 0; kx < 5; ++kx) {
+      const double v = (double)f[5 * ky + kx];
+      cs[kx] += v;
+      rs[ky] += v;
+    }
+  n = (cs[0] + cs[4]) + (cs[1] + cs[3]) + cs[2];
+  jx = R4 * (cs[4] - cs[0]) + R3 * (cs[3] - cs[1]);
+  jy = R4 * (rs[4] - rs[0]) + R3 * (rs[3] - rs[1]);
+  e = (R4 * R4) * ((cs[0] + cs[4]) + (rs[0] + rs[4])) + (R3 * R3) * ((cs[1] + cs[3]) + (rs[1] + rs[3]));
+  if (std::is_same<Real, float>::value) {
+    n += rho0;
+    e += 2.0 * rho0;
+  }
+}
+
+// Hermite equilibrium factor g_k(u, T) = W_k (1 + h_k(u, T)) (Eq. g_alpha,
+// N = 4, m = 1): h = u He1 + (th + u^2)/2 He2 + (u^3 + 3 u th)/6 He3
+//                 + (u^4 + 6 u^2 th + 3 th^2)/24 He4,  th = T - 1.
+__device__ __forceinline__ void hfac(double u, double th, double h[5]) {
+  const double u2 = u * u;
+  const double c1 = u;
+  const double c2 = 0.5 * (th + u2);
+  const double c3 = (1.0 / 6.0) * u * (u2 + 3.0 * th);
+  const double c4 = (1.0 / 24.0) * (u2 * u2 + 6.0 * u2 * th + 3.0 * th * th);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    h[k] = c1 * HE.v[1][k] + c2 * HE.v[2][k] + c3 * HE.v[3][k] + c4 * HE.v[4][k];
+  }
+}
+
+// f^eq of one node, stored form (FP64: f^eq; FP32: f^eq - w_k rho0).
+template <typename Real>
+__device__ __forceinline__ void feq25(double n, double ux, double uy, double T, double rho0,
+                                      Real out[25]) {
+  double hx[5], hy[5];
+  hfac(ux, T - 1.0, hx);
+  hfac(uy, T - 1.0, hy);
+#pragma unroll
+  for (int ky = 0; ky < 5; ++ky)
+#pragma unroll
+    for (int kx = 0; kx < 5; ++kx) {
+      const double w = Wk[kx] * Wk[ky];
+      if (std::is_same<Real, float>::value) {
+        const double dn = n - rho0;
+        out[5 * ky + kx] = (Real)(w * (dn * (1.0 + hx[kx]) * (1.0 + hy[ky]) +
+                                      rho0 * (hx[kx] + hy[ky] + hx[kx] * hy[ky])));
+      } else {
+        out[5 * ky + kx] = (Real)(n * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky])));
+      }
+    }
+}
+
+__device__ __forceinline__ double delta_p(double n, double T, double a, double b) {
+  // Delta p = p^i - p^w = nT - [nT/(1 - bn) - a n^2]
+  const double nT = n * T;
+  return nT - nT / (1.0 - b * n) + a * n * n;
+}
+
+// Running moment sums of a node's new populations, in population order; the
+// stage kernel accumulates them as it produces each population, and the set-up
+// kernels use the same sequence so that a restart is bitwise identical.
+__device__ __forceinline__ void carry_add(int k, double v, double& n, double& jx, double& jy,
+                                          double& e) {
+  const double px = Rk[k % 5], py = Rk[k / 5];
+  n += v;
+  jx += px * v;
+  jy += py * v;
+  e += (px * px + py * py) * v;
+}
+
+// (n, Delta p) of the carry from the running sums.
+template <bool F32>
+__device__ __forceinline__ void carry_finish(double n, double jx, double jy, double e, double rho0,
+                                             double va, double vb, double& n_out, double& dp_out) {
+  if (F32) {
+    n += rho0;
+    e += 2.0 * rho0;
+  }
+  const double in = 1.0 / n;
+  const double vx = jx * in, vy = jy * in;
+  n_out = n;
+  dp_out = delta_p(n, 0.5 * (e * in - vx * vx - vy * vy), va, vb);
+}
+
+// --------------------------------------------------------------------------
+// stage kernel
+// --------------------------------------------------------------------------
+
+template <typename Real, int BY, bool WALLS>
+__global__ void __launch_bounds__(64 * BY) stage_kernel(const StageArgs a) {
+  constexpr bool F32 = std::is_same<Real, float>::value;
+  constexpr int TW = 69;          // tile columns x0-3 .. x0+65
+  constexpr int TH = BY + 5;      // tile rows    y0-3 .. y0+BY+1
+  constexpr int TN = TW * TH;
+  constexpr int NT = 64 * BY;
+  constexpr int SLOTS = (TN + NT - 1) / NT;
+  constexpr int PB = TN * (int)sizeof(Real);
+  constexpr int MB = TN * (int)sizeof(double);
+  constexpr int BUF = 2 * (PB > MB ? PB : MB);
+  __shared__ __attribute__((aligned(16))) unsigned char lds[BUF];
+  __shared__ Real fy_sh[BY][64];
+  Real* const pl0 = reinterpret_cast<Real*>(lds);
+  Real* const pl1 = pl0 + TN;
+  double* const mn = reinterpret_cast<double*>(lds);
+  double* const mp = mn + TN;
+
+  // one wave per tile row: make the row index a scalar so that branches on
+  // it are uniform
+  const int tx = threadIdx.x, ty = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int tid = ty * 64 + tx;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int64_t ps = a.g.ps;
+
+  // XCD-aware tile order: consecutive workgroups go to different XCDs, so
+  // give each XCD a contiguous run of tiles (shared halos stay in one L2).
+  const int bid = blockIdx.x;
+  const int q8 = a.ntiles >> 3, r8 = a.ntiles & 7, xcd = bid & 7;
+  const int t = xcd * q8 + (xcd < r8 ? xcd : r8) + (bid >> 3);
+  const int tile_y = t / a.tiles_x, tile_x = t - tile_y * a.tiles_x;
+  const int x0 = tile_x * TILE_X, y0 = tile_y * (BY - 1);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool active = (tx < TILE_X) && (ty < BY - 1) && (x < nx) && (y < ny);
+
+  // storage offsets of this thread's tile slots (same for every population)
+  int soff[SLOTS], moff[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int i = tid + s * NT;
+    const int ii = i < TN ? i : TN - 1;
+    const int rr = ii / TW, cc = ii - rr * TW;
+    const int gx = wrapi(x0 - 3 + cc, nx);
+    const int gy = y0 - 3 + rr;
+    int sy, my;
+    if (WALLS) {
+      sy = min(max(gy, -3), ny + 2);
+      my = gy < 0 ? -1 - gy : (gy >= ny ? 2 * ny - 1 - gy : gy);
+      my = min(max(my, 0), ny - 1);
+    } else {
+      sy = wrapi(gy, ny);
+      my = sy;
+    }
+    soff[s] = (sy + 3) * nx + gx;
+    moff[s] = my * nx + gx;
+  }
+  const int oy = WALLS ? min(y, ny + 2) : wrapi(y, ny);
+  const int own = (oy + 3) * nx + wrapi(x, nx);
+
+  // no __restrict__: in the last RK stage f^n and f_dst are the same array
+  // (each node's f^n is read before its f_dst is written, by the same thread)
+  const Real* src = reinterpret_cast<const Real*>(a.fsrc);
+  const Real* fnp = reinterpret_cast<const Real*>(a.fn);
+  Real* dst = reinterpret_cast<Real*>(a.fdst);
+
+  // carried n and Delta p of f_src, tile + halo
+  {
+    const int64_t N = (int64_t)nx * ny;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int i = tid + s * NT;
+      if (i < TN) {
+        mn[i] = a.cin[moff[s]];
+        mp[i] = a.cin[N + moff[s]];
+      }
+    }
+  }
+
+  __syncthreads();
+
+  // force F = (1/n) grad Delta p + sigma grad lap n (Eq. F_def), 7x7 stencils
+  // of the carried fields.  Done before the 25 populations are loaded, and one
+  // column offset at a time (scheduling barriers), so that the stencil's ~100
+  // LDS reads never compete with f for registers.
+  double Fx, Fy;
+  {
+    const int cty = ty < BY - 1 ? ty : BY - 2;
+    const int ctx = tx < TILE_X ? tx : TILE_X - 1;
+    const int c = (cty + 3) * TW + (ctx + 3);
+    double gxs = 0.0, gys = 0.0, lxs = 0.0, lys = 0.0;
+#pragma unroll
+    for (int l = 1; l <= 3; ++l) {
+#pragma unroll
+      for (int m = -3; m <= 3; ++m) {
+        const int am = m < 0 ? -m : m;
+        if (GW[l][am] != 0.0) gxs += (l * GW[l][am]) * (mp[c + m * TW + l] - mp[c + m * TW - l]);
+        if (GL[l - 1][am] != 0.0) lxs += GL[l - 1][am] * (mn[c + m * TW + l] - mn[c + m * TW - l]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int m = -3; m <= 3; ++m) {
+        const int am = m < 0 ? -m : m;
+        if (GW[l][am] != 0.0) gys += (l * GW[l][am]) * (mp[c + l * TW + m] - mp[c - l * TW + m]);
+        if (GL[l - 1][am] != 0.0) lys += GL[l - 1][am] * (mn[c + l * TW + m] - mn[c - l * TW + m]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const double inv_nc = 1.0 / mn[c];
+    Fx = gxs * a.inv_ds * inv_nc + a.sigma * (lxs * a.inv_ds3);
+    Fy = gys * a.inv_ds * inv_nc + a.sigma * (lys * a.inv_ds3);
+  }
+
+  // own node: 25 populations and their moments
+  Real f[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) f[k] = src[k * ps + own];
+  double n, jx, jy, e;
+  sums25<Real>(f, a.rho0, n, jx, jy, e);
+  const double inv_n = 1.0 / n;
+  const double ux = jx * inv_n, uy = jy * inv_n;
+  const double T = 0.5 * (e * inv_n - ux * ux - uy * uy);
+
+  // Local part of L (Eq. ecast) for every population: BGK (f^eq - f)/tau and
+  // the force term -F.(grad_p f) with Eq. derf folded into M.  After this only
+  // loc[25] stays live; f itself is re-read from the LDS planes (own node) in
+  // the population loop.
+  Real loc[25];
+  {
+    double hx[5], hy[5];
+    hfac(ux, T - 1.0, hx);
+    hfac(uy, T - 1.0, hy);
+    const Real rit = (Real)a.inv_tau;
+    const double dn0 = n - a.rho0;
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+      const int kx = k % 5, ky = k / 5;
+      Real fe;
+      if (F32)
+        fe = (Real)(Wk[kx] * Wk[ky] *
+                    (dn0 * (1.0 + hx[kx]) * (1.0 + hy[ky]) + a.rho0 * (hx[kx] + hy[ky] + hx[kx] * hy[ky])));
+      else
+        fe = (Real)(n * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky])));
+      loc[k] = (fe - f[k]) * rit;
+    }
+  }
+  {
+    // force term, one velocity row (then column) at a time, folded into loc
+    // right away so that only five partial products are live at once
+    const Real rFx = (Real)Fx, rFy = (Real)Fy, rrho = (Real)a.rho0;
+#pragma unroll
+    for (int ky = 0; ky < 5; ++ky) {
+#pragma unroll
+      for (int kx = 0; kx < 5; ++kx) {
+        Real X = 0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) X += (Real)MT.v[kx][j] * f[5 * ky + j];
+        // M applied to the base w rho0 gives -p w rho0 along each axis
+        if (F32) X -= (Real)(Rk[kx] * Wk[kx] * Wk[ky]) * rrho;
+        loc[5 * ky + kx] -= rFx * X;
+      }
+    }
+#pragma unroll
+    for (int kx = 0; kx < 5; ++kx) {
+#pragma unroll
+      for (int ky = 0; ky < 5; ++ky) {
+        Real Y = 0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) Y += (Real)MT.v[ky][j] * f[5 * j + kx];
+        if (F32) Y -= (Real)(Rk[ky] * Wk[kx] * Wk[ky]) * rrho;
+        loc[5 * ky + kx] -= rFy * Y;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  const Real f12 = f[12];
+
+  const Real rdt = (Real)a.dt, rinv_ds = (Real)a.inv_ds;
+  const Real rA = (Real)a.A, rB = (Real)a.B;
+  const bool use_fn = a.A != 0.0;
+
+  // Materialise loc here: otherwise the stencil, moment and loc arithmetic
+  // is sunk past the barriers below into the population loop, and every
+  // stencil operand read from LDS stays live until then.
+#pragma unroll
+  for (int k = 0; k < 25; ++k) asm volatile("" : "+v"(loc[k]));
+  __syncthreads();  // the macroscopic tile is dead; its LDS becomes the planes
+
+  // prologue: plane of population 0
+  {
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int i = tid + s * NT;
+      if (i < TN) pl0[i] = src[soff[s]];
+    }
+  }
+  __syncthreads();
+
+  double dn = 0.0, djx = 0.0, djy = 0.0, de = 0.0;
+  const int rowc = (ty + 3) * TW + tx;   // x-face row values start here
+  const int colc = ty * TW + tx + 3;     // y-face column values start here
+  const int ownc = (ty + 3) * TW + tx + 3;
+
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    const int kx = k % 5, ky = k / 5;
+    const double px = Rk[kx], py = Rk[ky];
+    // next population that needs a plane (12 has p = 0 on both axes)
+    const int nk = (k == 11) ? 13 : k + 1;
+    const int ti = k < 12 ? k : k - 1;
+    const int nti = nk < 12 ? nk : nk - 1;
+    Real pre[SLOTS];
+    if (k != 12 && nk < 25) {
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) pre[s] = src[nk * ps + soff[s]];
+    }
+    const Real fnk = use_fn ? fnp[k * ps + own] : (Real)0;
+
+    Real L = loc[k];
+    Real fk = f12;
+    if (k != 12) {
+      const Real* P = (ti & 1) ? pl1 : pl0;
+      fk = P[ownc];
+      Real rxl = 0, ryl = 0;
+      if (kx != 2 && ty < BY - 1) {
+        const Real c0 = P[rowc], c1 = P[rowc + 1], c2 = P[rowc + 2], c3 = P[rowc + 3],
+                   c4 = P[rowc + 4], c5 = P[rowc + 5];
+        rxl = px > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (ky != 2) {
+        const Real c0 = P[colc], c1 = P[colc + TW], c2 = P[colc + 2 * TW], c3 = P[colc + 3 * TW],
+                   c4 = P[colc + 4 * TW], c5 = P[colc + 5 * TW];
+        ryl = py > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
+        fy_sh[ty][tx] = ryl;
+      }
+      const Real rxr = (kx != 2) ? __shfl_down(rxl, 1) : (Real)0;
+      __syncthreads();
+      Real adv = 0;
+      if (kx != 2) adv += (Real)px * (rxr - rxl);
+      if (ky != 2) {
+        const Real ryt = fy_sh[ty < BY - 1 ? ty + 1 : ty][tx];
+        adv += (Real)py * (ryt - ryl);
+      }
+      L -= adv * rinv_ds;
+    }
+
+    const Real out = rA * fnk + rB * (fk + rdt * L);
+    if (active) dst[k * ps + own] = out;
+    carry_add(k, (double)out, dn, djx, djy, de);
+
+    if (k != 12 && nk < 25) {
+      Real* Q = (nti & 1) ? pl1 : pl0;
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        const int i = tid + s * NT;
+        if (i < TN) Q[i] = pre[s];
+      }
+    }
+    if (k != 12) __syncthreads();
+  }
+
+  if (active) {
+    double cn, cdp;
+    carry_finish<F32>(dn, djx, djy, de, a.rho0, a.a, a.b, cn, cdp);
+    const int64_t N = (int64_t)nx * ny;
+    const int m = y * nx + x;
+    a.cout[m] = cn;
+    a.cout[N + m] = cdp;
+    if (!(fabs(cn) < INFINITY)) a.flag[0] = 1;
+  }
+}
+
+// --------------------------------------------------------------------------
+// diffuse-reflection ghosts (Sec. 3.4.2, walls across y)
+// --------------------------------------------------------------------------
+
+template <typename Real>
+__global__ void walls_kernel(const WallArgs a) {
+  constexpr bool F32 = std::is_same<Real, float>::value;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int wall = blockIdx.y;  // 0: lower wall (y = -1/2), 1: upper wall
+  const int nx = a.g.nx, ny = a.g.ny;
+  if (x >= nx) return;
+  Real* __restrict__ f = reinterpret_cast<Real*>(a.f);
+  const int64_t ps = a.g.ps;
+  // storage rows: interior y -> y + 3
+  const int r0 = wall ? ny + 2 : 3, r1 = wall ? ny + 1 : 4, r2 = wall ? ny : 5;
+  const int g1 = wall ? ny + 3 : 2, g2 = wall ? ny + 4 : 1, g3 = wall ? ny + 5 : 0;
+  const double Tw = wall ? a.tw[1] : a.tw[0];
+  const double uw = wall ? a.uw[1] : a.uw[0];
+
+  // populations travelling towards the wall (and p_y = 0): quadratic
+  // extrapolation; their WENO flux through the wall face
+  double out = 0.0;
+#pragma unroll
+  for (int ky = 0; ky < 5; ++ky) {
+    const bool towards = wall ? (ky >= 2) : (ky <= 2);
+    if (!towards) continue;
+#pragma unroll
+    for (int kx = 0; kx < 5; ++kx) {
+      const int k = 5 * ky + kx;
+      Real* pk = f + k * ps + x;
+      const Real v0 = pk[r0 * nx], v1 = pk[r1 * nx], v2 = pk[r2 * nx];
+      const Real e1 = (Real)3 * v0 - (Real)3 * v1 + v2;
+      const Real e2 = (Real)6 * v0 - (Real)8 * v1 + (Real)3 * v2;
+      const Real e3 = (Real)10 * v0 - (Real)15 * v1 + (Real)6 * v2;
+      pk[g1 * nx] = e1;
+      pk[g2 * nx] = e2;
+      pk[g3 * nx] = e3;
+      if (ky != 2) {
+        // face between the adjacent interior row and the first ghost row;
+        // upwind order (far interior ... ghost) is the same at both walls
+        double rec = (double)weno_rec(v2, v1, v0, e1, e2);
+        if (F32) rec += Wk[kx] * Wk[ky] * a.rho0;
+        out += Rk[ky] * rec;
+      }
+    }
+  }
+  // Eq. nw: the denominator sums g_kx(u_w, T_w) g_ky(0, T_w) p_ky over the
+  // wall-emitted velocities; sum_kx g_kx = 1 leaves sum_ky g_ky(0, T_w) p_ky.
+  double hx[5], hy[5];
+  hfac(uw, Tw - 1.0, hx);
+  hfac(0.0, Tw - 1.0, hy);
+  double den = 0.0;
+#pragma unroll
+  for (int ky = 0; ky < 5; ++ky) {
+    const bool emitted = wall ? (ky < 2) : (ky > 2);
+    if (emitted) den += Wk[ky] * (1.0 + hy[ky]) * Rk[ky];
+  }
+  const double nw = -out / den;
+  a.nw[wall * nx + x] = nw;
+#pragma unroll
+  for (int ky = 0; ky < 5; ++ky) {
+    const bool emitted = wall ? (ky < 2) : (ky > 2);
+    if (!emitted) continue;
+#pragma unroll
+    for (int kx = 0; kx < 5; ++kx) {
+      const int k = 5 * ky + kx;
+      double v = nw * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky]));
+      if (F32) v -= Wk[kx] * Wk[ky] * a.rho0;
+      Real* pk = f + k * ps + x;
+      pk[g1 * nx] = (Real)v;
+      pk[g2 * nx] = (Real)v;
+      pk[g3 * nx] = (Real)v;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// set-up and read-out
+// --------------------------------------------------------------------------
+
+template <typename Real>
+__global__ void init_kernel(Geometry g, const double* __restrict__ fld, Real* __restrict__ f,
+                            double* __restrict__ carry, double rho0, double va, double vb) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= g.nx) return;
+  const int64_t N = (int64_t)g.nx * g.ny;
+  const int m = y * g.nx + x;
+  Real fe[25];
+  feq25<Real>(fld[m], fld[N + m], fld[2 * N + m], fld[3 * N + m], rho0, fe);
+  const int own = (y + 3) * g.nx + x;
+  double n = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    f[k * g.ps + own] = fe[k];
+    carry_add(k, (double)fe[k], n, jx, jy, e);
+  }
+  carry_finish<std::is_same<Real, float>::value>(n, jx, jy, e, rho0, va, vb, carry[m], carry[N + m]);
+}
+
+template <typename Real>
+__device__ __forceinline__ void load_own(const Geometry& g, const Real* f, int x, int y, Real v[25]) {
+  const int own = (y + 3) * g.nx + x;
+#pragma unroll
+  for (int k = 0; k < 25; ++k) v[k] = f[k * g.ps + own];
+}
+
+template <typename Real>
+__global__ void moments_kernel(Geometry g, const Real* __restrict__ f, double* __restrict__ out,
+                               double rho0) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= g.nx) return;
+  Real v[25];
+  load_own(g, f, x, y, v);
+  double n, jx, jy, e;
+  sums25<Real>(v, rho0, n, jx, jy, e);
+  const double in = 1.0 / n, ux = jx * in, uy = jy * in;
+  const int64_t N = (int64_t)g.nx * g.ny;
+  const int m = y * g.nx + x;
+  out[m] = n;
+  out[N + m] = ux;
+  out[2 * N + m] = uy;
+  out[3 * N + m] = 0.5 * (e * in - ux * ux - uy * uy);
+}
+
+template <typename Real>
+__global__ void carry_kernel(Geometry g, const Real* __restrict__ f, double* __restrict__ carry,
+                             double rho0, double va, double vb) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= g.nx) return;
+  Real v[25];
+  load_own(g, f, x, y, v);
+  double n = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+#pragma unroll
+  for (int k = 0; k < 25; ++k) carry_add(k, (double)v[k], n, jx, jy, e);
+  const int64_t N = (int64_t)g.nx * g.ny;
+  const int m = y * g.nx + x;
+  carry_finish<std::is_same<Real, float>::value>(n, jx, jy, e, rho0, va, vb, carry[m], carry[N + m]);
+}
+
+template <typename Real>
+__global__ void pack_kernel(Geometry g, const Real* __restrict__ f, double* __restrict__ out,
+                            double rho0) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= g.nx) return;
+  const int64_t N = (int64_t)g.nx * g.ny;
+  const int own = (y + 3) * g.nx + x, m = y * g.nx + x;
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    double v = (double)f[k * g.ps + own];
+    if (std::is_same<Real, float>::value) v += Wk[k % 5] * Wk[k / 5] * rho0;
+    out[k * N + m] = v;
+  }
+}
+
+template <typename Real>
+__global__ void unpack_kernel(Geometry g, const double* __restrict__ in, Real* __restrict__ f,
+                              double rho0) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= g.nx) return;
+  const int64_t N = (int64_t)g.nx * g.ny;
+  const int own = (y + 3) * g.nx + x, m = y * g.nx + x;
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    double v = in[k * N + m];
+    if (std::is_same<Real, float>::value) v -= Wk[k % 5] * Wk[k / 5] * rho0;
+    f[k * g.ps + own] = (Real)v;
+  }
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+
+template <typename Real, int BY>
+static hipError_t stage_by(const StageArgs& a, hipStream_t s) {
+  dim3 block(64, BY);
+  dim3 grid(a.ntiles);
+  if (a.g.walls)
+    hipLaunchKernelGGL((stage_kernel<Real, BY, true>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((stage_kernel<Real, BY, false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(const StageArgs& a, int real_bytes, int by, hipStream_t s) {
+  if (real_bytes == 8) {
+    if (by == 16) return stage_by<double, 16>(a, s);
+    if (by == 8) return stage_by<double, 8>(a, s);
+  } else {
+    if (by == 16) return stage_by<float, 16>(a, s);
+    if (by == 8) return stage_by<float, 8>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_walls(const WallArgs& a, int real_bytes, hipStream_t s) {
+  dim3 block(64), grid((a.g.nx + 63) / 64, 2);
+  if (real_bytes == 8)
+    hipLaunchKernelGGL(walls_kernel<double>, grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL(walls_kernel<float>, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+static dim3 cell_grid(const Geometry& g) { return dim3((g.nx + 63) / 64, g.ny); }
+
+hipError_t launch_init(const Geometry& g, const double* fields, void* f, double* carry,
+                       double rho0, double va, double vb, int real_bytes, hipStream_t s) {
+  if (real_bytes == 8)
+    hipLaunchKernelGGL(init_kernel<double>, cell_grid(g), dim3(64), 0, s, g, fields,
+                       (double*)f, carry, rho0, va, vb);
+  else
+    hipLaunchKernelGGL(init_kernel<float>, cell_grid(g), dim3(64), 0, s, g, fields,
+                       (float*)f, carry, rho0, va, vb);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const Geometry& g, const void* f, double* out, double rho0,
+                          int real_bytes, hipStream_t s) {
+  if (real_bytes == 8)
+    hipLaunchKernelGGL(moments_kernel<double>, cell_grid(g), dim3(64), 0, s, g,
+                       (const double*)f, out, rho0);
+  else
+    hipLaunchKernelGGL(moments_kernel<float>, cell_grid(g), dim3(64), 0, s, g,
+                       (const float*)f, out, rho0);
+  return hipGetLastError();
+}
+
+hipError_t launch_carry(const Geometry& g, const void* f, double* carry, double rho0, double va,
+                        double vb, int real_bytes, hipStream_t s) {
+  if (real_bytes == 8)
+    hipLaunchKernelGGL(carry_kernel<double>, cell_grid(g), dim3(64), 0, s, g,
+                       (const double*)f, carry, rho0, va, vb);
+  else
+    hipLaunchKernelGGL(carry_kernel<float>, cell_grid(g), dim3(64), 0, s, g,
+                       (const float*)f, carry, rho0, va, vb);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const Geometry& g, const void* f, double* out, double rho0,
+                       int real_bytes, hipStream_t s) {
+  if (real_bytes == 8)
+    hipLaunchKernelGGL(pack_kernel<double>, cell_grid(g), dim3(64), 0, s, g, (const double*)f,
+                       out, rho0);
+  else
+    hipLaunchKernelGGL(pack_kernel<float>, cell_grid(g), dim3(64), 0, s, g, (const float*)f,
+                       out, rho0);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Geometry& g, const double* in, void* f, double rho0,
+                         int real_bytes, hipStream_t s) {
+  if (real_bytes == 8)
+    hipLaunchKernelGGL(unpack_kernel<double>, cell_grid(g), dim3(64), 0, s, g, in, (double*)f,
+                       rho0);
+  else
+    hipLaunchKernelGGL(unpack_kernel<float>, cell_grid(g), dim3(64), 0, s, g, in, (float*)f,
+                       rho0);
+  return hipGetLastError();
+}
+
+}  // namespace olbk

@@ -1,0 +1,233 @@
+"""ctypes binding of the gfx950 D2Q25 library (``libolb.so``, include/olb.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels.
+PyTorch supplies the device workspace (a uint8 CUDA tensor) and the stream.
+The functions keep the C names; ``Lattice`` bundles them for one context.
+There is no CPU fallback: without the built library or a GPU every call
+raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libolb.so")
+
+OLB_OK, OLB_E_ARG, OLB_E_CFL, OLB_E_DOMAIN, OLB_E_NONFINITE = 0, -1, -2, -3, -4
+OLB_E_WORKSPACE, OLB_E_DEVICE, OLB_E_STATE = -5, -6, -7
+OLB_BC_PERIODIC, OLB_BC_DIFFUSE = 0, 1
+OLB_FP64, OLB_FP32_MIXED = 0, 1
+
+
+class OlbError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"olb error {code}: {msg}")
+        self.code = code
+
+
+class olb_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("ds", ctypes.c_double), ("dt", ctypes.c_double), ("tau", ctypes.c_double),
+                ("a", ctypes.c_double), ("b", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+                ("tw_lo", ctypes.c_double), ("tw_hi", ctypes.c_double),
+                ("uw_lo", ctypes.c_double), ("uw_hi", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("rho_ref", ctypes.c_double)]
+
+
+_DEFAULTS = dict(bc_x=0, bc_y=0, tw_lo=1.0, tw_hi=1.0, uw_lo=0.0, uw_hi=0.0,
+                 precision=0, rho_ref=1.0, sigma=0.0)
+
+
+def make_params(d):
+    full = dict(_DEFAULTS)
+    full.update(d)
+    return olb_params(**{k: full[k] for k, _ in olb_params._fields_})
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_LIB = None
+
+# C name -> (argtypes, restype)
+_SIGS = {
+    "olb_workspace_bytes": ([ctypes.POINTER(olb_params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "olb_init": ([ctypes.POINTER(olb_params), _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "olb_set_fields": ([_vp, _dp, _dp, _dp, _dp], ctypes.c_int),
+    "olb_step": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "olb_sync": ([_vp], ctypes.c_int),
+    "olb_moments": ([_vp, _dp, _dp, _dp, _dp], ctypes.c_int),
+    "olb_moments_device": ([_vp, _vp], ctypes.c_int),
+    "olb_get_f": ([_vp, _dp], ctypes.c_int),
+    "olb_set_f": ([_vp, _dp], ctypes.c_int),
+    "olb_wall_density": ([_vp, _dp, _dp], ctypes.c_int),
+    "olb_set_tile": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "olb_launch_counts": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "olb_last_error": ([_vp], ctypes.c_char_p),
+    "olb_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "olb_free": ([_vp], None),
+}
+
+
+def lib():
+    """Load libolb.so; raises if it has not been built (no fallback)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _check(rc, h=None):
+    if rc != OLB_OK:
+        msg = lib().olb_last_error(h).decode() if h else lib().olb_strerror(rc).decode()
+        raise OlbError(rc, msg or lib().olb_strerror(rc).decode())
+
+
+# ------------------------------------------------------------ C-named calls --
+
+def olb_workspace_bytes(params):
+    p = make_params(params) if isinstance(params, dict) else params
+    n = ctypes.c_size_t()
+    _check(lib().olb_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return int(n.value)
+
+
+def olb_init(params, workspace_ptr, nbytes, stream_ptr):
+    p = make_params(params) if isinstance(params, dict) else params
+    h = _vp()
+    _check(lib().olb_init(ctypes.byref(p), _vp(workspace_ptr), nbytes, _vp(stream_ptr), ctypes.byref(h)))
+    return h
+
+
+def olb_set_fields(h, n, ux, uy, T):
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (n, ux, uy, T)]
+    _check(lib().olb_set_fields(h, *(_ptr(a) for a in arrs)), h)
+
+
+def olb_step(h, nsteps):
+    _check(lib().olb_step(h, int(nsteps)), h)
+
+
+def olb_sync(h):
+    _check(lib().olb_sync(h), h)
+
+
+def olb_moments(h, shape):
+    out = [np.empty(shape) for _ in range(4)]
+    _check(lib().olb_moments(h, *(_ptr(a) for a in out)), h)
+    return tuple(out)
+
+
+def olb_moments_device(h, dev_ptr):
+    _check(lib().olb_moments_device(h, _vp(dev_ptr)), h)
+
+
+def olb_get_f(h, shape):
+    f = np.empty((25,) + tuple(shape))
+    _check(lib().olb_get_f(h, _ptr(f)), h)
+    return f
+
+
+def olb_set_f(h, f):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    _check(lib().olb_set_f(h, _ptr(f)), h)
+
+
+def olb_wall_density(h, nx):
+    lo, hi = np.empty(nx), np.empty(nx)
+    _check(lib().olb_wall_density(h, _ptr(lo), _ptr(hi)), h)
+    return lo, hi
+
+
+def olb_set_tile(h, by):
+    _check(lib().olb_set_tile(h, int(by)), h)
+
+
+def olb_launch_counts(h):
+    s, w = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().olb_launch_counts(h, ctypes.byref(s), ctypes.byref(w)), h)
+    return s.value, w.value
+
+
+def olb_free(h):
+    lib().olb_free(h)
+
+
+# ------------------------------------------------------------- convenience --
+
+class Lattice:
+    """One context on ``device`` with a torch-owned workspace and stream."""
+
+    def __init__(self, params, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the D2Q25 library has no CPU path")
+        self.params = dict(_DEFAULTS)
+        self.params.update(params)
+        self.nx, self.ny = int(self.params["nx"]), int(self.params["ny"])
+        self.device = torch.device(device)
+        nbytes = olb_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = olb_init(self.params, aligned, nbytes, self.stream.cuda_stream)
+        self.nbytes = nbytes
+
+    def close(self):
+        if getattr(self, "h", None):
+            olb_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.ny, self.nx)
+
+    def set_fields(self, n, ux, uy, T):
+        olb_set_fields(self.h, n, ux, uy, T)
+
+    def step(self, nsteps=1):
+        olb_step(self.h, nsteps)
+
+    def sync(self):
+        olb_sync(self.h)
+
+    def moments(self):
+        return olb_moments(self.h, self.shape)
+
+    def moments_device(self, out):
+        olb_moments_device(self.h, out.data_ptr())
+
+    def get_f(self):
+        return olb_get_f(self.h, self.shape)
+
+    def set_f(self, f):
+        olb_set_f(self.h, f)
+
+    def wall_density(self):
+        return olb_wall_density(self.h, self.nx)
+
+    def set_tile(self, by):
+        olb_set_tile(self.h, by)
+
+    def launch_counts(self):
+        return olb_launch_counts(self.h)

@@ -86,16 +86,43 @@ def cpu_baseline(workload, sample_steps):
                       f"{sample_steps} RK3 steps, {dt:.1f} s"}
 
 
+def copy_kernel(gib, reps=10):
+    """Device-to-device copy of a known size: calibrates the HBM byte
+    counters (FETCH_SIZE / WRITE_SIZE per dispatch) and measures the copy
+    bandwidth this machine sustains."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3 / reps
+    moved = 2 * n * 8
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+                      "copy_GBps": round(moved / secs / 1e9, 1), "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="wave2048", choices=["wave2048", "spinodal4096"])
-    ap.add_argument("--tile", type=int, default=16, choices=[8, 16])
+    ap.add_argument("--tile", type=int, default=8, choices=[8, 16])
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only run a device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_gib > 0:
+        copy_kernel(args.copy_gib)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it "
               "(see the sharding notes in DESIGN.md)", file=sys.stderr)

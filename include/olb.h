@@ -125,7 +125,7 @@ olb_status olb_set_f(olb_ctx* c, const double* f);
  * OLB_E_STATE without walls.  Synchronous. */
 olb_status olb_wall_density(olb_ctx* c, double* nw_lo, double* nw_hi);
 
-/* Block height of the stage kernel: 16 (default) or 8 waves per workgroup;
+/* Block height of the stage kernel: 8 (default) or 16 waves per workgroup;
  * each workgroup updates 63 x (by - 1) nodes.  Results do not depend on it. */
 olb_status olb_set_tile(olb_ctx* c, int32_t by);
 

@@ -28,14 +28,12 @@ __device__ __forceinline__ int wrapi(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Reciprocal: hardware estimate refined by two Newton steps (FP64), or the
-// single-precision estimate (FP32).
+// Reciprocal: the hardware estimate (about 2^-23 relative) refined by one
+// Newton step (about 2^-46, far below what the weight normalisation below
+// needs), or the single-precision estimate (FP32).
 __device__ __forceinline__ double frcp(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = __builtin_fma(-d, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-d, r, 1.0);
-  return __builtin_fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(d);
+  return __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
 }
 __device__ __forceinline__ float frcp(float d) { return __builtin_amdgcn_rcpf(d); }
 
@@ -43,9 +41,11 @@ __device__ __forceinline__ float frcp(float d) { return __builtin_amdgcn_rcpf(d)
 // (f_{i-2}, f_{i-1}, f_i, f_{i+1}, f_{i+2}) (Eqs. weno5_flux..weno5_sigma).
 // No epsilon: when indicators vanish, the weights follow Tab. weno, i.e. the
 // ideal weights restricted to the vanishing candidates.  Indicators are formed
-// from first differences, so a vanishing indicator is exactly "three equal
-// values".  The weights use a single reciprocal:
-//   w_q ~ delta_q prod_{r != q} s_r^2.
+// from first differences d, so a vanishing indicator is exactly "three equal
+// values".  The unnormalised weights use a single reciprocal,
+//   w_q ~ delta_q prod_{r != q} s_r^2,  with delta scaled to (1, 6, 3),
+// and the three candidates enter as one combination of the d's:
+//   sum_q w_q (F^q - f_i) = [-2 w1 d1 + (5 w1 + w2) d2 + (2 w2 + 4 w3) d3 - w3 d4] / 6.
 __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, double v3, double v4) {
   const double d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
   const double a1 = d2 - d1, b1 = 3.0 * d2 - d1;
@@ -55,18 +55,15 @@ __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, doub
   const double s2 = (13.0 / 12.0) * a2 * a2 + 0.25 * b2 * b2;
   const double s3 = (13.0 / 12.0) * a3 * a3 + 0.25 * b3 * b3;
   const double q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
-  double w1 = D1 * q2 * q3, w2 = D2 * q1 * q3, w3 = D3 * q1 * q2;
+  double w1 = q2 * q3, w2 = 6.0 * (q1 * q3), w3 = 3.0 * (q1 * q2);
   const bool z1 = s1 == 0.0, z2 = s2 == 0.0, z3 = s3 == 0.0;
   if (z1 | z2 | z3) {
-    w1 = z1 ? D1 : 0.0;
-    w2 = z2 ? D2 : 0.0;
-    w3 = z3 ? D3 : 0.0;
+    w1 = z1 ? 1.0 : 0.0;
+    w2 = z2 ? 6.0 : 0.0;
+    w3 = z3 ? 3.0 : 0.0;
   }
-  // candidate values minus f_i
-  const double e1 = (5.0 / 6.0) * d2 - (1.0 / 3.0) * d1;
-  const double e2 = (1.0 / 6.0) * d2 + (1.0 / 3.0) * d3;
-  const double e3 = (2.0 / 3.0) * d3 - (1.0 / 6.0) * d4;
-  return v2 + (w1 * e1 + w2 * e2 + w3 * e3) * frcp(w1 + w2 + w3);
+  const double num = (5.0 * w1 + w2) * d2 - 2.0 * w1 * d1 + (2.0 * w2 + 4.0 * w3) * d3 - w3 * d4;
+  return v2 + num * frcp(6.0 * (w1 + w2 + w3));
 }
 
 // FP32 variant: the weights are invariant under scaling of f, so the first
@@ -85,17 +82,15 @@ __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3
   const float s2 = (13.0f / 12.0f) * a2 * a2 + 0.25f * b2 * b2;
   const float s3 = (13.0f / 12.0f) * a3 * a3 + 0.25f * b3 * b3;
   const float q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
-  float w1 = 0.1f * q2 * q3, w2 = 0.6f * q1 * q3, w3 = 0.3f * q1 * q2;
+  float w1 = q2 * q3, w2 = 6.0f * (q1 * q3), w3 = 3.0f * (q1 * q2);
   const bool z1 = q1 == 0.0f, z2 = q2 == 0.0f, z3 = q3 == 0.0f;
   if (z1 | z2 | z3) {
-    w1 = z1 ? 0.1f : 0.0f;
-    w2 = z2 ? 0.6f : 0.0f;
-    w3 = z3 ? 0.3f : 0.0f;
+    w1 = z1 ? 1.0f : 0.0f;
+    w2 = z2 ? 6.0f : 0.0f;
+    w3 = z3 ? 3.0f : 0.0f;
   }
-  const float e1 = (5.0f / 6.0f) * d2 - (1.0f / 3.0f) * d1;
-  const float e2 = (1.0f / 6.0f) * d2 + (1.0f / 3.0f) * d3;
-  const float e3 = (2.0f / 3.0f) * d3 - (1.0f / 6.0f) * d4;
-  return v2 + m * ((w1 * e1 + w2 * e2 + w3 * e3) * frcp(w1 + w2 + w3));
+  const float num = (5.0f * w1 + w2) * d2 - 2.0f * w1 * d1 + (2.0f * w2 + 4.0f * w3) * d3 - w3 * d4;
+  return v2 + m * (num * frcp(6.0f * (w1 + w2 + w3)));
 }
 
 // Moment sums of one node: n = sum f, j = sum p f, e = sum |p|^2 f.  With the
@@ -213,7 +208,7 @@ __global__ void __launch_bounds__(64 * BY) stage_kernel(const StageArgs a) {
   constexpr int MB = TN * (int)sizeof(double);
   constexpr int BUF = 2 * (PB > MB ? PB : MB);
   __shared__ __attribute__((aligned(16))) unsigned char lds[BUF];
-  __shared__ Real fy_sh[BY][64];
+  __shared__ Real fy_sh[2][BY][64];
   Real* const pl0 = reinterpret_cast<Real*>(lds);
   Real* const pl1 = pl0 + TN;
   double* const mn = reinterpret_cast<double*>(lds);
@@ -278,13 +273,13 @@ __global__ void __launch_bounds__(64 * BY) stage_kernel(const StageArgs a) {
       }
     }
   }
-
+  // population 12 (p = 0 on both axes) needs no halo: read its own value
+  const Real f12 = src[12 * ps + own];
   __syncthreads();
 
   // force F = (1/n) grad Delta p + sigma grad lap n (Eq. F_def), 7x7 stencils
-  // of the carried fields.  Done before the 25 populations are loaded, and one
-  // column offset at a time (scheduling barriers), so that the stencil's ~100
-  // LDS reads never compete with f for registers.
+  // of the carried fields, one column offset at a time (scheduling barriers
+  // keep the compiler from issuing all ~100 LDS reads at once).
   double Fx, Fy;
   {
     const int cty = ty < BY - 1 ? ty : BY - 2;
@@ -312,93 +307,48 @@ __global__ void __launch_bounds__(64 * BY) stage_kernel(const StageArgs a) {
     Fx = gxs * a.inv_ds * inv_nc + a.sigma * (lxs * a.inv_ds3);
     Fy = gys * a.inv_ds * inv_nc + a.sigma * (lys * a.inv_ds3);
   }
+  // materialise the force here, before the macroscopic tile's LDS is reused
+  asm volatile("" : "+v"(Fx));
+  asm volatile("" : "+v"(Fy));
 
-  // own node: 25 populations and their moments
-  Real f[25];
+  // Every population is streamed through LDS once.  As population k arrives,
+  // its contributions to
+  //   f_dst = A f^n + B (f + dt L),  L = -adv - F.(grad_p f) + (f^eq - f)/tau
+  // that do not need f^eq are accumulated: B (1 - dt/tau) f_k and
+  // -B dt adv_k into acc[k], and the force term (Eq. derf folded into M) is
+  // scattered into the accumulators of the populations sharing its velocity
+  // row (x-derivative) or column (y-derivative).  f^eq needs all 25
+  // populations (their moments) and is added at the end.
+  const double Bdt = a.B * a.dt;
+  const Real cx = (Real)(-Bdt * Fx), cy = (Real)(-Bdt * Fy);
+  const Real cb = (Real)(a.B * (1.0 - a.dt * a.inv_tau));
+  const Real cadv = (Real)(-Bdt * a.inv_ds);
+  Real acc[25];
 #pragma unroll
-  for (int k = 0; k < 25; ++k) f[k] = src[k * ps + own];
-  double n, jx, jy, e;
-  sums25<Real>(f, a.rho0, n, jx, jy, e);
-  const double inv_n = 1.0 / n;
-  const double ux = jx * inv_n, uy = jy * inv_n;
-  const double T = 0.5 * (e * inv_n - ux * ux - uy * uy);
-
-  // Local part of L (Eq. ecast) for every population: BGK (f^eq - f)/tau and
-  // the force term -F.(grad_p f) with Eq. derf folded into M.  After this only
-  // loc[25] stays live; f itself is re-read from the LDS planes (own node) in
-  // the population loop.
-  Real loc[25];
-  {
-    double hx[5], hy[5];
-    hfac(ux, T - 1.0, hx);
-    hfac(uy, T - 1.0, hy);
-    const Real rit = (Real)a.inv_tau;
-    const double dn0 = n - a.rho0;
-#pragma unroll
-    for (int k = 0; k < 25; ++k) {
-      const int kx = k % 5, ky = k / 5;
-      Real fe;
-      if (F32)
-        fe = (Real)(Wk[kx] * Wk[ky] *
-                    (dn0 * (1.0 + hx[kx]) * (1.0 + hy[ky]) + a.rho0 * (hx[kx] + hy[ky] + hx[kx] * hy[ky])));
-      else
-        fe = (Real)(n * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky])));
-      loc[k] = (fe - f[k]) * rit;
-    }
+  for (int k = 0; k < 25; ++k) {
+    // FP32 departure storage: M applied to the base w rho0 gives -p w rho0
+    acc[k] = F32 ? (Real)(Bdt * a.rho0 * (Fx * Rk[k % 5] + Fy * Rk[k / 5]) * Wk[k % 5] * Wk[k / 5])
+                 : (Real)0;
   }
-  {
-    // force term, one velocity row (then column) at a time, folded into loc
-    // right away so that only five partial products are live at once
-    const Real rFx = (Real)Fx, rFy = (Real)Fy, rrho = (Real)a.rho0;
-#pragma unroll
-    for (int ky = 0; ky < 5; ++ky) {
-#pragma unroll
-      for (int kx = 0; kx < 5; ++kx) {
-        Real X = 0;
-#pragma unroll
-        for (int j = 0; j < 5; ++j) X += (Real)MT.v[kx][j] * f[5 * ky + j];
-        // M applied to the base w rho0 gives -p w rho0 along each axis
-        if (F32) X -= (Real)(Rk[kx] * Wk[kx] * Wk[ky]) * rrho;
-        loc[5 * ky + kx] -= rFx * X;
-      }
-    }
-#pragma unroll
-    for (int kx = 0; kx < 5; ++kx) {
-#pragma unroll
-      for (int ky = 0; ky < 5; ++ky) {
-        Real Y = 0;
-#pragma unroll
-        for (int j = 0; j < 5; ++j) Y += (Real)MT.v[ky][j] * f[5 * j + kx];
-        if (F32) Y -= (Real)(Rk[ky] * Wk[kx] * Wk[ky]) * rrho;
-        loc[5 * ky + kx] -= rFy * Y;
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  const Real f12 = f[12];
 
-  const Real rdt = (Real)a.dt, rinv_ds = (Real)a.inv_ds;
-  const Real rA = (Real)a.A, rB = (Real)a.B;
-  const bool use_fn = a.A != 0.0;
-
-  // Materialise loc here: otherwise the stencil, moment and loc arithmetic
-  // is sunk past the barriers below into the population loop, and every
-  // stencil operand read from LDS stays live until then.
-#pragma unroll
-  for (int k = 0; k < 25; ++k) asm volatile("" : "+v"(loc[k]));
   __syncthreads();  // the macroscopic tile is dead; its LDS becomes the planes
 
-  // prologue: plane of population 0
+  // population order of the 24 planes (12 has none); plane t lives in buffer
+  // t & 1 and its face-exchange row in fy_sh[t & 1]
+  auto tile_pop = [](int t) { return t < 12 ? t : t + 1; };
+  Real pre[SLOTS];
   {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int i = tid + s * NT;
       if (i < TN) pl0[i] = src[soff[s]];
     }
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) pre[s] = src[1 * ps + soff[s]];
   }
   __syncthreads();
 
-  double dn = 0.0, djx = 0.0, djy = 0.0, de = 0.0;
+  double sn = 0.0, sjx = 0.0, sjy = 0.0, se = 0.0;   // moments of f_src
   const int rowc = (ty + 3) * TW + tx;   // x-face row values start here
   const int colc = ty * TW + tx + 3;     // y-face column values start here
   const int ownc = (ty + 3) * TW + tx + 3;
@@ -407,21 +357,26 @@ __global__ void __launch_bounds__(64 * BY) stage_kernel(const StageArgs a) {
   for (int k = 0; k < 25; ++k) {
     const int kx = k % 5, ky = k / 5;
     const double px = Rk[kx], py = Rk[ky];
-    // next population that needs a plane (12 has p = 0 on both axes)
-    const int nk = (k == 11) ? 13 : k + 1;
-    const int ti = k < 12 ? k : k - 1;
-    const int nti = nk < 12 ? nk : nk - 1;
-    Real pre[SLOTS];
-    if (k != 12 && nk < 25) {
+    Real fk, adv = 0;
+    if (k == 12) {
+      fk = f12;
+    } else {
+      const int ti = k < 12 ? k : k - 1;
+      Real* const P = (ti & 1) ? pl1 : pl0;
+      // stage plane ti + 1 (loaded during the previous population) and
+      // start loading plane ti + 2
+      if (ti + 1 < 24) {
+        Real* const Q = (ti & 1) ? pl0 : pl1;
 #pragma unroll
-      for (int s = 0; s < SLOTS; ++s) pre[s] = src[nk * ps + soff[s]];
-    }
-    const Real fnk = use_fn ? fnp[k * ps + own] : (Real)0;
-
-    Real L = loc[k];
-    Real fk = f12;
-    if (k != 12) {
-      const Real* P = (ti & 1) ? pl1 : pl0;
+        for (int s = 0; s < SLOTS; ++s) {
+          const int i = tid + s * NT;
+          if (i < TN) Q[i] = pre[s];
+        }
+      }
+      if (ti + 2 < 24) {
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) pre[s] = src[tile_pop(ti + 2) * ps + soff[s]];
+      }
       fk = P[ownc];
       Real rxl = 0, ryl = 0;
       if (kx != 2 && ty < BY - 1) {
@@ -434,32 +389,60 @@ __global__ void __launch_bounds__(64 * BY) stage_kernel(const StageArgs a) {
         const Real c0 = P[colc], c1 = P[colc + TW], c2 = P[colc + 2 * TW], c3 = P[colc + 3 * TW],
                    c4 = P[colc + 4 * TW], c5 = P[colc + 5 * TW];
         ryl = py > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
-        fy_sh[ty][tx] = ryl;
+        fy_sh[ti & 1][ty][tx] = ryl;
       }
       const Real rxr = (kx != 2) ? __shfl_down(rxl, 1) : (Real)0;
       __syncthreads();
-      Real adv = 0;
       if (kx != 2) adv += (Real)px * (rxr - rxl);
       if (ky != 2) {
-        const Real ryt = fy_sh[ty < BY - 1 ? ty + 1 : ty][tx];
+        const Real ryt = fy_sh[ti & 1][ty < BY - 1 ? ty + 1 : ty][tx];
         adv += (Real)py * (ryt - ryl);
       }
-      L -= adv * rinv_ds;
     }
+    carry_add(k, (double)fk, sn, sjx, sjy, se);
+    acc[k] += cb * fk + cadv * adv;
+    const Real tfx = cx * fk, tfy = cy * fk;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      acc[5 * ky + i] += (Real)MT.v[i][kx] * tfx;
+      acc[5 * i + kx] += (Real)MT.v[i][ky] * tfy;
+    }
+    // do the updates now: left alone, the compiler sinks them to the end of
+    // the kernel and keeps every population's inputs live until then
+#pragma unroll
+    for (int i = 0; i < 25; ++i) asm volatile("" : "+v"(acc[i]));
+    asm volatile("" : "+v"(sn), "+v"(sjx), "+v"(sjy), "+v"(se));
+  }
 
-    const Real out = rA * fnk + rB * (fk + rdt * L);
+  // moments of f_src, equilibrium (Eqs. feq, g_alpha), RK combine
+  if (F32) {
+    sn += a.rho0;
+    se += 2.0 * a.rho0;
+  }
+  const double inv_n = 1.0 / sn;
+  const double ux = sjx * inv_n, uy = sjy * inv_n;
+  const double T = 0.5 * (se * inv_n - ux * ux - uy * uy);
+  double hx[5], hy[5];
+  hfac(ux, T - 1.0, hx);
+  hfac(uy, T - 1.0, hy);
+  const double cfe = Bdt * a.inv_tau;
+  const double dn0 = sn - a.rho0;
+  const Real rA = (Real)a.A;
+  const bool use_fn = a.A != 0.0;
+  double dn = 0.0, djx = 0.0, djy = 0.0, de = 0.0;
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    const int kx = k % 5, ky = k / 5;
+    Real fe;
+    if (F32)
+      fe = (Real)(cfe * Wk[kx] * Wk[ky] *
+                  (dn0 * (1.0 + hx[kx]) * (1.0 + hy[ky]) + a.rho0 * (hx[kx] + hy[ky] + hx[kx] * hy[ky])));
+    else
+      fe = (Real)(cfe * (sn * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky]))));
+    const Real fnk = use_fn ? fnp[k * ps + own] : (Real)0;
+    const Real out = rA * fnk + (acc[k] + fe);
     if (active) dst[k * ps + own] = out;
     carry_add(k, (double)out, dn, djx, djy, de);
-
-    if (k != 12 && nk < 25) {
-      Real* Q = (nti & 1) ? pl1 : pl0;
-#pragma unroll
-      for (int s = 0; s < SLOTS; ++s) {
-        const int i = tid + s * NT;
-        if (i < TN) Q[i] = pre[s];
-      }
-    }
-    if (k != 12) __syncthreads();
   }
 
   if (active) {

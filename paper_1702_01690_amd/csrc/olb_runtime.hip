@@ -162,7 +162,7 @@ olb_status olb_init(const olb_params* p, void* dev_workspace, size_t bytes, void
   c->flag = (int*)(c->ws + 3 * L.buf + 2 * L.carry + L.nw);
   c->cur = 0;
   c->have_f = false;
-  c->by = 16;
+  c->by = 8;
   c->g.nx = p->nx;
   c->g.ny = p->ny;
   c->g.ps = (int64_t)(p->ny + 6) * p->nx;

@@ -57,13 +57,29 @@ def load_traffic(workload):
     return entry.get("bytes_per_launch")
 
 
-def make_case(workload):
+WORKLOADS = {
+    "wave2048": "2048x2048 periodic FP64, shear + longitudinal waves, vdW a=9/49 b=2/21, T=1, "
+                "tau=0.005, dt=5e-4, ds=1/64",
+    "spinodal4096": "4096x4096 periodic FP32-mixed spinodal decomposition at T=0.9 T_c, "
+                    "n=3.5(1+-1% noise), tau=0.005, dt=2e-4, ds=1/320",
+    "channels": "256 walled channels (nx 64..512, ny 128..1024, 43.6 M nodes), FP32-mixed, "
+                "T_w in [0.7, 0.95] T_c, one launch per stage over all channels, graphs of 10 steps",
+}
+
+
+def make_cases(workload):
     import olb_inputs as I
     if workload == "wave2048":
-        return I.wave2048(), 0
+        c = I.wave2048()
+        c.params["precision"] = 0
+        return [c]
     if workload == "spinodal4096":
         c = I.spinodal(4096, 4096)
-        return c, 1
+        c.params["precision"] = 1
+        c.params["rho_ref"] = I.N_CRIT
+        return [c]
+    if workload == "channels":
+        return I.channels()
     raise SystemExit(f"unknown workload {workload}")
 
 
@@ -72,7 +88,12 @@ def cpu_baseline(workload, sample_steps):
     2048^2 field is this crop tiled, so the per-cell work is identical)."""
     import olb_inputs as I
     import oracle
-    case = I.wave64() if workload == "wave2048" else I.spinodal(64, 64)
+    if workload == "wave2048":
+        case = I.wave64()
+    elif workload == "spinodal4096":
+        case = I.spinodal(64, 64)
+    else:
+        case = I.channel(64, 128, tw=0.8 * I.T_CRIT)
     o = oracle.Oracle(case.params)
     o.set_fields(*case.fields)
     o.step(1)
@@ -82,7 +103,7 @@ def cpu_baseline(workload, sample_steps):
     cells = case.params["nx"] * case.params["ny"]
     return {"value": cells * sample_steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.get_threads(),
             "kind": "oracle",
-            "sample": f"{case.params['nx']}x{case.params['ny']} crop of the same workload, "
+            "sample": f"{case.params['nx']}x{case.params['ny']} lattice of the same physics (FP64 oracle), "
                       f"{sample_steps} RK3 steps, {dt:.1f} s"}
 
 
@@ -113,7 +134,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="wave2048", choices=["wave2048", "spinodal4096"])
+    ap.add_argument("--workload", default="wave2048", choices=sorted(WORKLOADS))
+    ap.add_argument("--graph", type=int, default=10, help="RK3 steps per HIP graph (batches)")
+    ap.add_argument("--autotune", action="store_true", help="pick the tile height by trial (batches)")
     ap.add_argument("--tile", type=int, default=8, choices=[8, 16])
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
@@ -131,18 +154,31 @@ def main():
     import torch
     from paper_1702_01690_amd import olb
 
-    case, precision = make_case(args.workload)
-    params = dict(case.params)
-    params["precision"] = precision
-    if precision == 1:
-        params["rho_ref"] = float(np.mean(case.n))
-    lat = olb.Lattice(params, device="cuda:0")
-    lat.set_tile(args.tile)
-    lat.set_fields(*case.fields)
-    stream = lat.stream
-    cells = case.params["nx"] * case.params["ny"]
-    print(f"[bench] {args.workload} {case.params['nx']}x{case.params['ny']} precision={precision} "
+    cases = make_cases(args.workload)
+    precision = cases[0].params["precision"]
+    batched = args.workload == "channels"
+    cells = sum(c.params["nx"] * c.params["ny"] for c in cases)
+    print(f"[bench] {args.workload} instances={len(cases)} nodes={cells} precision={precision} "
           f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    if batched:
+        lat = olb.Batch([c.params for c in cases], device="cuda:0")
+        if args.autotune:
+            lat.autotune(trial_steps=2)
+        else:
+            lat.set_tile(args.tile)
+        if args.graph:
+            lat.use_graph(args.graph)
+        for i, c in enumerate(cases):
+            lat.set_fields(i, *c.fields)
+        n_stage, n_walls = 3, 3
+        tile_by = lat.tiles()[1]
+    else:
+        lat = olb.Lattice(cases[0].params, device="cuda:0")
+        lat.set_tile(args.tile)
+        lat.set_fields(*cases[0].fields)
+        n_stage, n_walls = lat.launch_counts()
+        tile_by = args.tile
+    stream = lat.stream
 
     lat.step(args.warmup)
     lat.sync()
@@ -159,9 +195,9 @@ def main():
     ms_events = ev0.elapsed_time(ev1)
     secs = ms_events / 1e3
     mlups = cells * args.steps / secs / 1e6
-    n_stage, n_walls = lat.launch_counts()
     launches = n_stage * args.steps
-    avg_launch_s = secs / launches            # only stage kernels run in the region
+    # the region holds the stage launches (and, with walls, the small ghost launches)
+    avg_launch_s = secs / launches
     rb = 8 if precision == 0 else 4
     bytes_per_launch = ALG_VALUES_PER_CELL_STEP * rb * cells / n_stage
     achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
@@ -186,7 +222,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.workload, args.cpu_steps if args.workload == "wave2048" else 20)
+        cpu = cpu_baseline(args.workload, args.cpu_steps if args.workload == "wave2048" else 40)
 
     out = {
         "metric": "MLUPS per full RK3 step (D2Q25)",
@@ -201,10 +237,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if precision == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload,
-                   "lattice": f"{case.params['nx']}x{case.params['ny']}",
-                   "boundary": "periodic", "tau": case.params["tau"], "dt": case.params["dt"],
-                   "ds": case.params["ds"], "tile": f"63x{args.tile - 1}",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "nodes": cells, "instances": len(cases), "tile": f"63x{tile_by - 1}",
                    "wall_s": round(wall, 3)},
         "roofline": roof,
         "cpu_baseline": cpu,

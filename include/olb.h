@@ -137,6 +137,44 @@ const char* olb_last_error(const olb_ctx* c);
 const char* olb_strerror(olb_status s);
 void olb_free(olb_ctx* c);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent instances advanced in lockstep, every RK stage
+ * being ONE kernel launch over the tiles of all instances (plus one wall-
+ * ghost launch with walls).  Instances may differ in every parameter except
+ * precision and boundary kind.  Ownership, errors and host layouts are those
+ * of the single-instance calls; i selects an instance (0 <= i < count).
+ * ------------------------------------------------------------------------ */
+typedef struct olb_batch olb_batch;
+
+/* Workspace for count instances with parameters p[0..count-1]. */
+olb_status olb_batch_workspace_bytes(const olb_params* p, int32_t count, size_t* bytes);
+olb_status olb_batch_init(const olb_params* p, int32_t count, void* dev_workspace, size_t bytes,
+                          void* hip_stream, olb_batch** out);
+olb_status olb_batch_set_fields(olb_batch* b, int32_t i, const double* n, const double* ux,
+                                const double* uy, const double* T);
+olb_status olb_batch_set_f(olb_batch* b, int32_t i, const double* f);
+olb_status olb_batch_get_f(olb_batch* b, int32_t i, double* f);
+/* nsteps RK-3 steps of every instance (all must have f).  Asynchronous. */
+olb_status olb_batch_step(olb_batch* b, int32_t nsteps);
+olb_status olb_batch_sync(olb_batch* b);
+olb_status olb_batch_moments(olb_batch* b, int32_t i, double* n, double* ux, double* uy, double* T);
+olb_status olb_batch_wall_density(olb_batch* b, int32_t i, double* nw_lo, double* nw_hi);
+/* Replay olb_batch_step in HIP graphs of steps_per_graph RK-3 steps (rounded
+ * up to even; 0 = direct launches).  Captured on first use; needs a
+ * non-default stream.  Results are bitwise those of direct launches. */
+olb_status olb_batch_use_graph(olb_batch* b, int32_t steps_per_graph);
+olb_status olb_batch_set_tile(olb_batch* b, int32_t by);
+/* Choose the stage tile height (8 or 16) by timing trial_steps steps of each
+ * on a uniform rest state of every instance; the choice is read from / added
+ * to the JSON file cache_path (NULL: no cache).  The trial overwrites the
+ * instances: set their fields afterwards.  chosen_by may be NULL. */
+olb_status olb_batch_autotune(olb_batch* b, int32_t trial_steps, const char* cache_path,
+                              int32_t* chosen_by);
+/* Tiles per stage launch and the current tile height. */
+olb_status olb_batch_tiles(const olb_batch* b, int32_t* tiles, int32_t* by);
+const char* olb_batch_last_error(const olb_batch* b);
+void olb_batch_free(olb_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@ struct Geometry {
   int walls;       // 1: diffuse walls across y, 0: periodic y
 };
 
+// One RK stage of one instance, as the tile function sees it.
 struct StageArgs {
   Geometry g;
   const void* fsrc;     // f^(s-1)
@@ -27,23 +28,44 @@ struct StageArgs {
   double inv_ds, inv_ds3, dt, inv_tau, a, b, sigma;
   double A, B;          // f_dst = A f^n + B (f_src + dt L[f_src])
   double rho0;          // FP32 departure base (f = w_k rho0 + stored value)
-  int tiles_x, ntiles;
 };
 
-struct WallArgs {
+// One lattice instance of a batch (device table, ascending tile_base).
+struct InstDesc {
   Geometry g;
-  void* f;              // the stage's source array; ghost rows are written
+  void* f[3];           // f^n, f^(1), f^(2)
+  double* carry[2];     // carried (n, Delta p), ping-pong
   double* nw;           // [2][nx] wall densities (lower, upper)
+  double inv_ds, inv_ds3, dt, inv_tau, a, b, sigma, rho0;
   double tw[2], uw[2];  // lower / upper wall temperature and tangential velocity
-  double rho0;
+  int tiles_x, tiles_y; // stage tiles of 63 x (BY - 1) nodes
+  int tile_base;        // first tile of this instance in the batch's tile queue
+  int wall_block_base;  // first 64-column block of this instance (walls)
+};
+
+struct BatchArgs {
+  const InstDesc* inst;
+  int ninst, total_tiles;
+  int stage;            // 0, 1, 2: f_src = f[stage], f_dst = f[(stage + 1) % 3]
+  int cur;              // carry[cur] belongs to f_src
+  int* flag;            // set to 1 when a non-finite density is produced
+  double A, B;          // f_dst = A f^n + B (f_src + dt L[f_src])
+};
+
+struct WallBatchArgs {
+  const InstDesc* inst;
+  int ninst;
+  int stage;            // ghost rows are written into f[stage]
 };
 
 // Tile geometry of the stage kernel: 64 lanes across x produce 63 cells, BY
 // waves across y produce BY - 1 rows.
 constexpr int TILE_X = 63;
 
-hipError_t launch_stage(const StageArgs& a, int real_bytes, int by, hipStream_t s);
-hipError_t launch_walls(const WallArgs& a, int real_bytes, hipStream_t s);
+// One workgroup per tile of the batch's tile queue.
+hipError_t launch_stage(const BatchArgs& a, int real_bytes, int by, bool walls, hipStream_t s);
+// wall_blocks: sum over instances of ceil(nx / 64).
+hipError_t launch_walls(const WallBatchArgs& a, int real_bytes, int wall_blocks, hipStream_t s);
 // f = f^eq(n, u, T) from device fields [4][ny][nx]; also writes the carry.
 hipError_t launch_init(const Geometry& g, const double* fields, void* f, double* carry,
                        double rho0, double a, double b, int real_bytes, hipStream_t s);

@@ -1,73 +1,53 @@
 // olb_runtime.hip -- host runtime behind the C-ABI of include/olb.h.
 //
-// A context owns no device memory: it carves the caller's workspace into
-//   A, B, C   three distribution arrays (25 planes of (ny + 6) x nx values:
-//             f^n and the two RK-3 intermediates)
-//   carry[2]  the carried (n, Delta p) of the current and the next stage
-//   nw        wall densities of the last stage
+// An engine holds one or more lattice instances that advance in lockstep.
+// It owns no device memory: it carves the caller's workspace into
+//   desc      the device table of instances (InstDesc)
 //   flag      non-finite flag
-// and enqueues all device work on the caller's stream.  B and C double as a
-// staging area for host transfers (they hold no state between steps).
+//   per instance: A, B, C (f^n and the two RK-3 intermediates, 25 planes of
+//             (ny + 6) x nx values), carry[2] (carried n and Delta p,
+//             ping-pong) and nw (wall densities)
+// and enqueues all device work on the caller's stream.  Every stage is one
+// launch over the tile queue of all instances (plus one wall-ghost launch
+// with walls).  B and C double as staging for host transfers.  A single
+// context (olb_ctx) is an engine with one instance; olb_batch exposes N.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
+#include <vector>
 
 #include "../../include/olb.h"
 #include "olb_consts.hpp"
 #include "olb_device.hpp"
-
-struct olb_ctx {
-  olb_params p;
-  hipStream_t stream;
-  unsigned char* ws;
-  size_t ws_bytes;
-  int rb;             // bytes per stored distribution value (8 or 4)
-  size_t buf_bytes;   // bytes of one distribution array
-  void* f[3];
-  double* carry[2];
-  double* nw;
-  int* flag;
-  int cur;            // carry index of the current f
-  bool have_f;
-  int by;             // stage-kernel block height (8 or 16)
-  olbk::Geometry g;
-  std::string err;
-};
 
 namespace {
 
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
-struct Layout {
-  size_t buf, carry, nw, flag, total;
+struct InstLayout {
+  size_t buf, carry, nw, total;
 };
 
-Layout layout_of(const olb_params& p) {
-  Layout L;
+InstLayout inst_layout(const olb_params& p) {
+  InstLayout L;
   const size_t rb = p.precision == OLB_FP32_MIXED ? 4 : 8;
   const size_t N = (size_t)p.nx * (size_t)p.ny;
   L.buf = align_up(25 * (size_t)(p.ny + 6) * (size_t)p.nx * rb);
   L.carry = align_up(2 * N * sizeof(double));
   L.nw = align_up(2 * (size_t)p.nx * sizeof(double));
-  L.flag = ALIGN;
-  L.total = 3 * L.buf + 2 * L.carry + L.nw + L.flag;
+  L.total = 3 * L.buf + 2 * L.carry + L.nw;
   return L;
 }
 
-olb_status set_err(olb_ctx* c, olb_status s, const std::string& msg) {
-  if (c) c->err = msg;
-  return s;
-}
-
-olb_status hip_check(olb_ctx* c, hipError_t e, const char* what) {
-  if (e == hipSuccess) return OLB_OK;
-  return set_err(c, OLB_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
+size_t head_bytes(int count) { return align_up((size_t)count * sizeof(olbk::InstDesc)) + ALIGN; }
 
 olb_status validate(const olb_params* p, std::string& why) {
   if (!p) { why = "null params"; return OLB_E_ARG; }
@@ -89,7 +69,8 @@ olb_status validate(const olb_params* p, std::string& why) {
   }
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) { why = "tau must be positive"; return OLB_E_DOMAIN; }
   if (p->bc_y == OLB_BC_DIFFUSE &&
-      (!(p->tw_lo > 0.0) || !(p->tw_hi > 0.0) || !std::isfinite(p->uw_lo) || !std::isfinite(p->uw_hi))) {
+      (!(p->tw_lo > 0.0) || !(p->tw_hi > 0.0) || !std::isfinite(p->tw_lo) ||
+       !std::isfinite(p->tw_hi) || !std::isfinite(p->uw_lo) || !std::isfinite(p->uw_hi))) {
     why = "wall temperatures must be positive"; return OLB_E_DOMAIN;
   }
   // CFL condition (Sec. 4.1): p_max dt / (m ds) < 1 with p_max = sqrt(5 + sqrt 10)
@@ -97,249 +78,529 @@ olb_status validate(const olb_params* p, std::string& why) {
   return OLB_OK;
 }
 
-olb_status check_fields(olb_ctx* c, const double* n, const double* ux, const double* uy,
-                        const double* T) {
-  const size_t N = (size_t)c->p.nx * c->p.ny;
-  const double nmax = c->p.b > 0.0 ? 1.0 / c->p.b : INFINITY;
-  for (size_t i = 0; i < N; ++i) {
-    if (!std::isfinite(ux[i]) || !std::isfinite(uy[i]))
-      return set_err(c, OLB_E_DOMAIN, "non-finite velocity");
-    if (!(n[i] > 0.0) || !(n[i] < nmax) || !std::isfinite(n[i]))
-      return set_err(c, OLB_E_DOMAIN, "density outside (0, 1/b)");
-    if (!(T[i] > 0.0) || !std::isfinite(T[i])) return set_err(c, OLB_E_DOMAIN, "temperature <= 0");
+olb_status validate_batch(const olb_params* p, int32_t count, std::string& why) {
+  if (!p || count < 1) { why = "need at least one instance"; return OLB_E_ARG; }
+  for (int32_t i = 0; i < count; ++i) {
+    olb_status s = validate(p + i, why);
+    if (s) {
+      why = "instance " + std::to_string(i) + ": " + why;
+      return s;
+    }
+    if (p[i].precision != p[0].precision || p[i].bc_y != p[0].bc_y) {
+      why = "all instances of a batch share precision and boundary kind";
+      return OLB_E_ARG;
+    }
   }
-  return OLB_OK;
-}
-
-double rho0_of(const olb_ctx* c) { return c->p.precision == OLB_FP32_MIXED ? c->p.rho_ref : 0.0; }
-
-olb_status read_flag(olb_ctx* c) {
-  int h = 0;
-  olb_status s = hip_check(c, hipMemcpyAsync(&h, c->flag, sizeof h, hipMemcpyDeviceToHost, c->stream),
-                           "flag copy");
-  if (s) return s;
-  s = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
-  if (s) return s;
-  if (h) return set_err(c, OLB_E_NONFINITE, "a non-finite density was produced");
   return OLB_OK;
 }
 
 }  // namespace
 
+struct Engine {
+  std::vector<olb_params> p;
+  std::vector<olbk::InstDesc> desc;  // host copy of the device table
+  std::vector<bool> have_f;
+  hipStream_t stream = nullptr;
+  unsigned char* ws = nullptr;
+  size_t ws_bytes = 0;
+  olbk::InstDesc* d_desc = nullptr;
+  int* flag = nullptr;
+  int rb = 8;
+  bool walls = false;
+  int by = 8;
+  int cur = 0;                     // carry index of the current f^n
+  int total_tiles = 0, wall_blocks = 0;
+  int graph_steps = 0;             // 0: direct launches
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::string err;
+
+  int count() const { return (int)p.size(); }
+
+  olb_status fail(olb_status s, const std::string& msg) {
+    err = msg;
+    return s;
+  }
+  olb_status hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return OLB_OK;
+    return fail(OLB_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+  double rho0(int i) const { return p[i].precision == OLB_FP32_MIXED ? p[i].rho_ref : 0.0; }
+
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
+
+  // tile counts for the current block height, and the device table
+  olb_status upload_desc() {
+    int tiles = 0, blocks = 0;
+    for (int i = 0; i < count(); ++i) {
+      olbk::InstDesc& d = desc[i];
+      d.tiles_x = (p[i].nx + olbk::TILE_X - 1) / olbk::TILE_X;
+      d.tiles_y = (p[i].ny + (by - 1) - 1) / (by - 1);
+      d.tile_base = tiles;
+      d.wall_block_base = blocks;
+      tiles += d.tiles_x * d.tiles_y;
+      blocks += (p[i].nx + 63) / 64;
+    }
+    total_tiles = tiles;
+    wall_blocks = blocks;
+    drop_graph();
+    olb_status s = hip(hipMemcpyAsync(d_desc, desc.data(), desc.size() * sizeof(olbk::InstDesc),
+                                      hipMemcpyHostToDevice, stream), "descriptor upload");
+    if (s) return s;
+    return hip(hipStreamSynchronize(stream), "stream sync");
+  }
+
+  olb_status init(const olb_params* params, int32_t n, void* workspace, size_t bytes, void* strm) {
+    p.assign(params, params + n);
+    have_f.assign(n, false);
+    stream = (hipStream_t)strm;
+    ws = (unsigned char*)workspace;
+    ws_bytes = bytes;
+    rb = p[0].precision == OLB_FP32_MIXED ? 4 : 8;
+    walls = p[0].bc_y == OLB_BC_DIFFUSE;
+    d_desc = (olbk::InstDesc*)ws;
+    flag = (int*)(ws + align_up((size_t)n * sizeof(olbk::InstDesc)));
+    size_t off = head_bytes(n);
+    desc.resize(n);
+    for (int i = 0; i < n; ++i) {
+      const InstLayout L = inst_layout(p[i]);
+      olbk::InstDesc& d = desc[i];
+      std::memset(&d, 0, sizeof d);
+      d.g.nx = p[i].nx;
+      d.g.ny = p[i].ny;
+      d.g.ps = (int64_t)(p[i].ny + 6) * p[i].nx;
+      d.g.walls = walls;
+      for (int k = 0; k < 3; ++k) d.f[k] = ws + off + k * L.buf;
+      d.carry[0] = (double*)(ws + off + 3 * L.buf);
+      d.carry[1] = (double*)(ws + off + 3 * L.buf + L.carry);
+      d.nw = (double*)(ws + off + 3 * L.buf + 2 * L.carry);
+      d.inv_ds = 1.0 / p[i].ds;
+      d.inv_ds3 = 1.0 / (p[i].ds * p[i].ds * p[i].ds);
+      d.dt = p[i].dt;
+      d.inv_tau = 1.0 / p[i].tau;
+      d.a = p[i].a;
+      d.b = p[i].b;
+      d.sigma = p[i].sigma;
+      d.rho0 = rho0(i);
+      d.tw[0] = p[i].tw_lo;
+      d.tw[1] = p[i].tw_hi;
+      d.uw[0] = p[i].uw_lo;
+      d.uw[1] = p[i].uw_hi;
+      off += L.total;
+    }
+    // zero everything once (ghost rows of periodic lattices are never written)
+    olb_status s = hip(hipMemsetAsync(ws, 0, off, stream), "workspace clear");
+    if (s) return s;
+    return upload_desc();
+  }
+
+  olb_status check_index(int i) {
+    if (i < 0 || i >= count()) return fail(OLB_E_ARG, "instance index out of range");
+    return OLB_OK;
+  }
+
+  olb_status check_fields(int i, const double* n, const double* ux, const double* uy, const double* T) {
+    const size_t N = (size_t)p[i].nx * p[i].ny;
+    const double nmax = p[i].b > 0.0 ? 1.0 / p[i].b : INFINITY;
+    for (size_t k = 0; k < N; ++k) {
+      if (!std::isfinite(ux[k]) || !std::isfinite(uy[k])) return fail(OLB_E_DOMAIN, "non-finite velocity");
+      if (!(n[k] > 0.0) || !(n[k] < nmax) || !std::isfinite(n[k]))
+        return fail(OLB_E_DOMAIN, "density outside (0, 1/b)");
+      if (!(T[k] > 0.0) || !std::isfinite(T[k])) return fail(OLB_E_DOMAIN, "temperature <= 0");
+    }
+    return OLB_OK;
+  }
+
+  // f = f^eq of device fields [4][ny][nx] already in instance i's staging area
+  olb_status init_from_staging(int i) {
+    const olbk::InstDesc& d = desc[i];
+    olb_status s = hip(olbk::launch_init(d.g, (const double*)d.f[1], d.f[0], d.carry[cur], d.rho0,
+                                         d.a, d.b, rb, stream), "init kernel");
+    if (s) return s;
+    have_f[i] = true;
+    return OLB_OK;
+  }
+
+  olb_status set_fields(int i, const double* n, const double* ux, const double* uy, const double* T) {
+    olb_status s = check_index(i);
+    if (s) return s;
+    if (!n || !ux || !uy || !T) return fail(OLB_E_ARG, "null field");
+    s = check_fields(i, n, ux, uy, T);
+    if (s) return s;
+    const size_t N = (size_t)p[i].nx * p[i].ny;
+    double* stage = (double*)desc[i].f[1];
+    const double* src[4] = {n, ux, uy, T};
+    for (int k = 0; k < 4; ++k) {
+      s = hip(hipMemcpyAsync(stage + k * N, src[k], N * sizeof(double), hipMemcpyHostToDevice, stream),
+              "field upload");
+      if (s) return s;
+    }
+    s = init_from_staging(i);
+    if (s) return s;
+    s = hip(hipMemsetAsync(flag, 0, sizeof(int), stream), "flag clear");
+    if (s) return s;
+    return hip(hipStreamSynchronize(stream), "stream sync");
+  }
+
+  olb_status set_f(int i, const double* f) {
+    olb_status s = check_index(i);
+    if (s) return s;
+    if (!f) return fail(OLB_E_ARG, "null f");
+    const olbk::InstDesc& d = desc[i];
+    const size_t N = (size_t)p[i].nx * p[i].ny;
+    s = hip(hipMemcpyAsync(d.f[1], f, 25 * N * sizeof(double), hipMemcpyHostToDevice, stream), "f upload");
+    if (s) return s;
+    s = hip(olbk::launch_unpack(d.g, (const double*)d.f[1], d.f[0], d.rho0, rb, stream), "unpack kernel");
+    if (s) return s;
+    s = hip(olbk::launch_carry(d.g, d.f[0], d.carry[cur], d.rho0, d.a, d.b, rb, stream), "carry kernel");
+    if (s) return s;
+    s = hip(hipMemsetAsync(flag, 0, sizeof(int), stream), "flag clear");
+    if (s) return s;
+    have_f[i] = true;
+    return hip(hipStreamSynchronize(stream), "stream sync");
+  }
+
+  olb_status read_flag() {
+    int h = 0;
+    olb_status s = hip(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, stream), "flag copy");
+    if (s) return s;
+    s = hip(hipStreamSynchronize(stream), "stream sync");
+    if (s) return s;
+    if (h) return fail(OLB_E_NONFINITE, "a non-finite density was produced");
+    return OLB_OK;
+  }
+
+  olb_status get_f(int i, double* f) {
+    olb_status s = check_index(i);
+    if (s) return s;
+    if (!f) return fail(OLB_E_ARG, "null f");
+    if (!have_f[i]) return fail(OLB_E_STATE, "no distribution set");
+    const olbk::InstDesc& d = desc[i];
+    const size_t N = (size_t)p[i].nx * p[i].ny;
+    s = hip(olbk::launch_pack(d.g, d.f[0], (double*)d.f[1], d.rho0, rb, stream), "pack kernel");
+    if (s) return s;
+    s = hip(hipMemcpyAsync(f, d.f[1], 25 * N * sizeof(double), hipMemcpyDeviceToHost, stream), "f download");
+    if (s) return s;
+    return read_flag();
+  }
+
+  olb_status moments_device(int i, double* out) {
+    olb_status s = check_index(i);
+    if (s) return s;
+    if (!out) return fail(OLB_E_ARG, "null output");
+    if (!have_f[i]) return fail(OLB_E_STATE, "no distribution set");
+    const olbk::InstDesc& d = desc[i];
+    return hip(olbk::launch_moments(d.g, d.f[0], out, d.rho0, rb, stream), "moments kernel");
+  }
+
+  olb_status moments(int i, double* n, double* ux, double* uy, double* T) {
+    olb_status s = check_index(i);
+    if (s) return s;
+    if (!n || !ux || !uy || !T) return fail(OLB_E_ARG, "null output");
+    const size_t N = (size_t)p[i].nx * p[i].ny;
+    double* stage = (double*)desc[i].f[1];
+    s = moments_device(i, stage);
+    if (s) return s;
+    double* dst[4] = {n, ux, uy, T};
+    for (int k = 0; k < 4; ++k) {
+      s = hip(hipMemcpyAsync(dst[k], stage + k * N, N * sizeof(double), hipMemcpyDeviceToHost, stream),
+              "moments download");
+      if (s) return s;
+    }
+    return read_flag();
+  }
+
+  olb_status wall_density(int i, double* lo, double* hi) {
+    olb_status s = check_index(i);
+    if (s) return s;
+    if (!lo || !hi) return fail(OLB_E_ARG, "null output");
+    if (!walls) return fail(OLB_E_STATE, "no walls");
+    const size_t nx = (size_t)p[i].nx;
+    s = hip(hipMemcpyAsync(lo, desc[i].nw, nx * sizeof(double), hipMemcpyDeviceToHost, stream), "nw download");
+    if (s) return s;
+    s = hip(hipMemcpyAsync(hi, desc[i].nw + nx, nx * sizeof(double), hipMemcpyDeviceToHost, stream),
+            "nw download");
+    if (s) return s;
+    return hip(hipStreamSynchronize(stream), "stream sync");
+  }
+
+  // one RK-3 step: per stage, wall ghosts of f_src (with walls), then the
+  // stage launch over every instance's tiles
+  olb_status enqueue_step() {
+    for (int s = 0; s < 3; ++s) {
+      if (walls) {
+        olbk::WallBatchArgs wa{d_desc, count(), s};
+        olb_status e = hip(olbk::launch_walls(wa, rb, wall_blocks, stream), "wall kernel");
+        if (e) return e;
+      }
+      olbk::BatchArgs ba;
+      ba.inst = d_desc;
+      ba.ninst = count();
+      ba.total_tiles = total_tiles;
+      ba.stage = s;
+      ba.cur = cur;
+      ba.flag = flag;
+      ba.A = olbc::RK_A[s];
+      ba.B = olbc::RK_B[s];
+      olb_status e = hip(olbk::launch_stage(ba, rb, by, walls, stream), "stage kernel");
+      if (e) return e;
+      cur ^= 1;
+    }
+    return OLB_OK;
+  }
+
+  olb_status step(int32_t nsteps) {
+    if (nsteps < 0) return fail(OLB_E_ARG, "negative step count");
+    for (int i = 0; i < count(); ++i)
+      if (!have_f[i]) return fail(OLB_E_STATE, "step before every instance has f (set_fields / set_f)");
+    int32_t left = nsteps;
+    // graph replays: graph_steps is even, so the carry index returns to 0
+    while (graph_steps > 0 && left >= graph_steps && cur == 0) {
+      if (!graph_exec) {
+        olb_status s = hip(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "graph capture");
+        if (s) return fail(OLB_E_STATE, err + " (graphs need a non-default stream)");
+        for (int k = 0; k < graph_steps; ++k) {
+          s = enqueue_step();
+          if (s) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            cur = 0;
+            return s;
+          }
+        }
+        s = hip(hipStreamEndCapture(stream, &graph), "graph capture end");
+        if (s) return s;
+        s = hip(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0), "graph instantiate");
+        if (s) return s;
+        cur = 0;  // capture enqueued nothing on the device
+      }
+      olb_status s = hip(hipGraphLaunch(graph_exec, stream), "graph launch");
+      if (s) return s;
+      left -= graph_steps;
+    }
+    for (int32_t k = 0; k < left; ++k) {
+      olb_status s = enqueue_step();
+      if (s) return s;
+    }
+    return OLB_OK;
+  }
+
+  olb_status set_tile(int32_t b) {
+    if (b != 8 && b != 16) return fail(OLB_E_ARG, "tile height must be 8 or 16");
+    if (b == by) return OLB_OK;
+    by = b;
+    return upload_desc();
+  }
+
+  // uniform rest state (n = rho_ref or 1, T = wall temperature or 1) in every
+  // instance, for timing trials
+  olb_status fill_rest_state() {
+    for (int i = 0; i < count(); ++i) {
+      const size_t N = (size_t)p[i].nx * p[i].ny;
+      std::vector<double> h(4 * N);
+      const double n0 = p[i].precision == OLB_FP32_MIXED ? p[i].rho_ref : 1.0;
+      const double T0 = walls ? p[i].tw_lo : 1.0;
+      for (size_t k = 0; k < N; ++k) {
+        h[k] = n0;
+        h[N + k] = 0.0;
+        h[2 * N + k] = 0.0;
+        h[3 * N + k] = T0;
+      }
+      olb_status s = hip(hipMemcpyAsync(desc[i].f[1], h.data(), 4 * N * sizeof(double),
+                                        hipMemcpyHostToDevice, stream), "trial upload");
+      if (s) return s;
+      s = init_from_staging(i);
+      if (s) return s;
+      s = hip(hipStreamSynchronize(stream), "stream sync");
+      if (s) return s;
+    }
+    return OLB_OK;
+  }
+
+  std::string tune_key() const {
+    long long nodes = 0;
+    for (const auto& q : p) nodes += (long long)q.nx * q.ny;
+    std::ostringstream k;
+    k << (rb == 8 ? "fp64" : "fp32") << (walls ? "-walls" : "-periodic") << "-n" << count()
+      << "-nodes" << nodes;
+    return k.str();
+  }
+
+  static bool read_cache(const char* path, const std::string& key, int& b) {
+    if (!path) return false;
+    std::ifstream in(path);
+    if (!in) return false;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    const std::string text = ss.str();
+    const std::string pat = "\"" + key + "\"";
+    size_t at = text.find(pat);
+    if (at == std::string::npos) return false;
+    at = text.find("\"by\":", at);
+    if (at == std::string::npos) return false;
+    b = std::atoi(text.c_str() + at + 5);
+    return b == 8 || b == 16;
+  }
+
+  static void write_cache(const char* path, const std::string& key, int b, const double ms[2]) {
+    if (!path) return;
+    // keep other keys: naive merge by rewriting the object
+    std::string body;
+    {
+      std::ifstream in(path);
+      if (in) {
+        std::stringstream ss;
+        ss << in.rdbuf();
+        body = ss.str();
+      }
+    }
+    std::ostringstream entry;
+    entry << "\"" << key << "\": {\"by\": " << b << ", \"ms_per_step_by8\": " << ms[0]
+          << ", \"ms_per_step_by16\": " << ms[1] << "}";
+    std::string out;
+    const size_t open = body.find('{'), close = body.rfind('}');
+    if (open == std::string::npos || close == std::string::npos || body.find("\"" + key + "\"") != std::string::npos) {
+      out = "{\n " + entry.str() + "\n}\n";
+    } else {
+      std::string inner = body.substr(open + 1, close - open - 1);
+      while (!inner.empty() && (inner.back() == '\n' || inner.back() == ' ')) inner.pop_back();
+      out = "{" + inner + (inner.find_first_not_of(" \n") == std::string::npos ? "\n " : ",\n ") +
+            entry.str() + "\n}\n";
+    }
+    std::ofstream o(path);
+    o << out;
+  }
+
+  olb_status autotune(int32_t trial_steps, const char* cache_path, int32_t* chosen) {
+    if (trial_steps < 1) return fail(OLB_E_ARG, "trial_steps must be >= 1");
+    const std::string key = tune_key();
+    int best = 0;
+    if (read_cache(cache_path, key, best)) {
+      olb_status s = set_tile(best);
+      if (s) return s;
+      if (chosen) *chosen = best;
+      return OLB_OK;
+    }
+    double ms[2] = {0.0, 0.0};
+    const int cand[2] = {8, 16};
+    const int saved_graph = graph_steps;
+    graph_steps = 0;
+    hipEvent_t e0, e1;
+    olb_status s = hip(hipEventCreate(&e0), "event");
+    if (s) return s;
+    s = hip(hipEventCreate(&e1), "event");
+    if (s) return s;
+    for (int c = 0; c < 2 && !s; ++c) {
+      s = set_tile(cand[c]);
+      if (!s) s = fill_rest_state();
+      if (!s) s = step(1);
+      if (!s) s = hip(hipEventRecord(e0, stream), "event record");
+      if (!s) s = step(trial_steps);
+      if (!s) s = hip(hipEventRecord(e1, stream), "event record");
+      if (!s) s = hip(hipEventSynchronize(e1), "event sync");
+      float t = 0.0f;
+      if (!s) s = hip(hipEventElapsedTime(&t, e0, e1), "event time");
+      ms[c] = t / trial_steps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    graph_steps = saved_graph;
+    for (int i = 0; i < count(); ++i) have_f[i] = false;  // trial states are discarded
+    if (s) return s;
+    best = ms[0] <= ms[1] ? 8 : 16;
+    s = set_tile(best);
+    if (s) return s;
+    write_cache(cache_path, key, best, ms);
+    if (chosen) *chosen = best;
+    return OLB_OK;
+  }
+
+  ~Engine() { drop_graph(); }
+};
+
+struct olb_ctx {
+  Engine e;
+};
+struct olb_batch {
+  Engine e;
+};
+
+static size_t engine_bytes(const olb_params* p, int32_t n) {
+  size_t total = head_bytes(n);
+  for (int32_t i = 0; i < n; ++i) total += inst_layout(p[i]).total;
+  return total;
+}
+
+template <typename H>
+static olb_status make_engine(const olb_params* p, int32_t n, void* ws, size_t bytes, void* stream,
+                              H** out) {
+  if (!out) return OLB_E_ARG;
+  *out = nullptr;
+  std::string why;
+  olb_status s = validate_batch(p, n, why);
+  if (s) return s;
+  if (!ws || bytes < engine_bytes(p, n) || ((uintptr_t)ws % ALIGN) != 0) return OLB_E_WORKSPACE;
+  H* h = new (std::nothrow) H();
+  if (!h) return OLB_E_WORKSPACE;
+  s = h->e.init(p, n, ws, bytes, stream);
+  if (s) {
+    delete h;
+    return s;
+  }
+  *out = h;
+  return OLB_OK;
+}
+
 extern "C" {
+
+// ------------------------------------------------------------ one instance --
 
 olb_status olb_workspace_bytes(const olb_params* p, size_t* bytes) {
   std::string why;
   if (!bytes) return OLB_E_ARG;
   olb_status s = validate(p, why);
   if (s) return s;
-  *bytes = layout_of(*p).total;
+  *bytes = engine_bytes(p, 1);
   return OLB_OK;
 }
 
 olb_status olb_init(const olb_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
                     olb_ctx** out) {
-  if (!out) return OLB_E_ARG;
-  *out = nullptr;
-  std::string why;
-  olb_status s = validate(p, why);
-  if (s) return s;
-  const Layout L = layout_of(*p);
-  if (!dev_workspace || bytes < L.total || ((uintptr_t)dev_workspace % ALIGN) != 0)
-    return OLB_E_WORKSPACE;
-  olb_ctx* c = new (std::nothrow) olb_ctx();
-  if (!c) return OLB_E_WORKSPACE;
-  c->p = *p;
-  c->stream = (hipStream_t)hip_stream;
-  c->ws = (unsigned char*)dev_workspace;
-  c->ws_bytes = bytes;
-  c->rb = p->precision == OLB_FP32_MIXED ? 4 : 8;
-  c->buf_bytes = L.buf;
-  for (int i = 0; i < 3; ++i) c->f[i] = c->ws + i * L.buf;
-  c->carry[0] = (double*)(c->ws + 3 * L.buf);
-  c->carry[1] = (double*)(c->ws + 3 * L.buf + L.carry);
-  c->nw = (double*)(c->ws + 3 * L.buf + 2 * L.carry);
-  c->flag = (int*)(c->ws + 3 * L.buf + 2 * L.carry + L.nw);
-  c->cur = 0;
-  c->have_f = false;
-  c->by = 8;
-  c->g.nx = p->nx;
-  c->g.ny = p->ny;
-  c->g.ps = (int64_t)(p->ny + 6) * p->nx;
-  c->g.walls = p->bc_y == OLB_BC_DIFFUSE;
-  // zero everything once: ghost rows of periodic lattices are never written
-  s = hip_check(c, hipMemsetAsync(c->ws, 0, L.total, c->stream), "workspace clear");
-  if (!s) s = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
-  if (s) {
-    delete c;
-    return s;
-  }
-  *out = c;
-  return OLB_OK;
+  return make_engine(p, 1, dev_workspace, bytes, hip_stream, out);
 }
 
 olb_status olb_set_fields(olb_ctx* c, const double* n, const double* ux, const double* uy,
                           const double* T) {
-  if (!c || !n || !ux || !uy || !T) return OLB_E_ARG;
-  olb_status s = check_fields(c, n, ux, uy, T);
-  if (s) return s;
-  const size_t N = (size_t)c->p.nx * c->p.ny;
-  double* stage = (double*)c->f[1];
-  const double* src[4] = {n, ux, uy, T};
-  for (int i = 0; i < 4; ++i) {
-    s = hip_check(c, hipMemcpyAsync(stage + i * N, src[i], N * sizeof(double), hipMemcpyHostToDevice,
-                                    c->stream), "field upload");
-    if (s) return s;
-  }
-  s = hip_check(c, olbk::launch_init(c->g, stage, c->f[0], c->carry[0], rho0_of(c), c->p.a, c->p.b,
-                                     c->rb, c->stream), "init kernel");
-  if (s) return s;
-  s = hip_check(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream), "flag clear");
-  if (s) return s;
-  c->cur = 0;
-  c->have_f = true;
-  return hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
+  return c ? c->e.set_fields(0, n, ux, uy, T) : OLB_E_ARG;
 }
-
-olb_status olb_step(olb_ctx* c, int32_t nsteps) {
-  if (!c || nsteps < 0) return OLB_E_ARG;
-  if (!c->have_f) return set_err(c, OLB_E_STATE, "olb_step before olb_set_fields / olb_set_f");
-  const olb_params& p = c->p;
-  olbk::StageArgs a;
-  a.g = c->g;
-  a.flag = c->flag;
-  a.inv_ds = 1.0 / p.ds;
-  a.inv_ds3 = 1.0 / (p.ds * p.ds * p.ds);
-  a.dt = p.dt;
-  a.inv_tau = 1.0 / p.tau;
-  a.a = p.a;
-  a.b = p.b;
-  a.sigma = p.sigma;
-  a.rho0 = rho0_of(c);
-  a.tiles_x = (p.nx + olbk::TILE_X - 1) / olbk::TILE_X;
-  const int tiles_y = (p.ny + (c->by - 1) - 1) / (c->by - 1);
-  a.ntiles = a.tiles_x * tiles_y;
-  olbk::WallArgs w;
-  w.g = c->g;
-  w.nw = c->nw;
-  w.tw[0] = p.tw_lo;
-  w.tw[1] = p.tw_hi;
-  w.uw[0] = p.uw_lo;
-  w.uw[1] = p.uw_hi;
-  w.rho0 = a.rho0;
-  for (int32_t st = 0; st < nsteps; ++st) {
-    for (int s = 0; s < 3; ++s) {
-      void* src = c->f[s];                 // A, B, C
-      void* dst = c->f[(s + 1) % 3];       // B, C, A
-      if (c->g.walls) {
-        w.f = src;
-        olb_status e = hip_check(c, olbk::launch_walls(w, c->rb, c->stream), "wall kernel");
-        if (e) return e;
-      }
-      a.fsrc = src;
-      a.fn = c->f[0];
-      a.fdst = dst;
-      a.cin = c->carry[c->cur];
-      a.cout = c->carry[c->cur ^ 1];
-      a.A = olbc::RK_A[s];
-      a.B = olbc::RK_B[s];
-      olb_status e = hip_check(c, olbk::launch_stage(a, c->rb, c->by, c->stream), "stage kernel");
-      if (e) return e;
-      c->cur ^= 1;
-    }
-  }
-  return OLB_OK;
-}
-
-olb_status olb_sync(olb_ctx* c) {
-  if (!c) return OLB_E_ARG;
-  return read_flag(c);
-}
-
-olb_status olb_moments_device(olb_ctx* c, double* dev_out) {
-  if (!c || !dev_out) return OLB_E_ARG;
-  if (!c->have_f) return set_err(c, OLB_E_STATE, "no distribution set");
-  return hip_check(c, olbk::launch_moments(c->g, c->f[0], dev_out, rho0_of(c), c->rb, c->stream),
-                   "moments kernel");
-}
-
+olb_status olb_step(olb_ctx* c, int32_t nsteps) { return c ? c->e.step(nsteps) : OLB_E_ARG; }
+olb_status olb_sync(olb_ctx* c) { return c ? c->e.read_flag() : OLB_E_ARG; }
 olb_status olb_moments(olb_ctx* c, double* n, double* ux, double* uy, double* T) {
-  if (!c || !n || !ux || !uy || !T) return OLB_E_ARG;
-  if (!c->have_f) return set_err(c, OLB_E_STATE, "no distribution set");
-  const size_t N = (size_t)c->p.nx * c->p.ny;
-  double* stage = (double*)c->f[1];
-  olb_status s = olb_moments_device(c, stage);
-  if (s) return s;
-  double* dst[4] = {n, ux, uy, T};
-  for (int i = 0; i < 4; ++i) {
-    s = hip_check(c, hipMemcpyAsync(dst[i], stage + i * N, N * sizeof(double), hipMemcpyDeviceToHost,
-                                    c->stream), "moments download");
-    if (s) return s;
-  }
-  return read_flag(c);
+  return c ? c->e.moments(0, n, ux, uy, T) : OLB_E_ARG;
 }
-
-olb_status olb_get_f(olb_ctx* c, double* f) {
-  if (!c || !f) return OLB_E_ARG;
-  if (!c->have_f) return set_err(c, OLB_E_STATE, "no distribution set");
-  const size_t N = (size_t)c->p.nx * c->p.ny;
-  double* stage = (double*)c->f[1];
-  olb_status s = hip_check(c, olbk::launch_pack(c->g, c->f[0], stage, rho0_of(c), c->rb, c->stream),
-                           "pack kernel");
-  if (s) return s;
-  s = hip_check(c, hipMemcpyAsync(f, stage, 25 * N * sizeof(double), hipMemcpyDeviceToHost, c->stream),
-                "f download");
-  if (s) return s;
-  return read_flag(c);
+olb_status olb_moments_device(olb_ctx* c, double* dev_out) {
+  return c ? c->e.moments_device(0, dev_out) : OLB_E_ARG;
 }
-
-olb_status olb_set_f(olb_ctx* c, const double* f) {
-  if (!c || !f) return OLB_E_ARG;
-  const size_t N = (size_t)c->p.nx * c->p.ny;
-  double* stage = (double*)c->f[1];
-  olb_status s = hip_check(c, hipMemcpyAsync(stage, f, 25 * N * sizeof(double), hipMemcpyHostToDevice,
-                                             c->stream), "f upload");
-  if (s) return s;
-  s = hip_check(c, olbk::launch_unpack(c->g, stage, c->f[0], rho0_of(c), c->rb, c->stream),
-                "unpack kernel");
-  if (s) return s;
-  s = hip_check(c, olbk::launch_carry(c->g, c->f[0], c->carry[0], rho0_of(c), c->p.a, c->p.b, c->rb,
-                                      c->stream), "carry kernel");
-  if (s) return s;
-  s = hip_check(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream), "flag clear");
-  if (s) return s;
-  c->cur = 0;
-  c->have_f = true;
-  return hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
+olb_status olb_get_f(olb_ctx* c, double* f) { return c ? c->e.get_f(0, f) : OLB_E_ARG; }
+olb_status olb_set_f(olb_ctx* c, const double* f) { return c ? c->e.set_f(0, f) : OLB_E_ARG; }
+olb_status olb_wall_density(olb_ctx* c, double* lo, double* hi) {
+  return c ? c->e.wall_density(0, lo, hi) : OLB_E_ARG;
 }
-
-olb_status olb_wall_density(olb_ctx* c, double* nw_lo, double* nw_hi) {
-  if (!c || !nw_lo || !nw_hi) return OLB_E_ARG;
-  if (!c->g.walls) return set_err(c, OLB_E_STATE, "no walls");
-  const size_t nx = (size_t)c->p.nx;
-  olb_status s = hip_check(c, hipMemcpyAsync(nw_lo, c->nw, nx * sizeof(double), hipMemcpyDeviceToHost,
-                                             c->stream), "nw download");
-  if (s) return s;
-  s = hip_check(c, hipMemcpyAsync(nw_hi, c->nw + nx, nx * sizeof(double), hipMemcpyDeviceToHost,
-                                  c->stream), "nw download");
-  if (s) return s;
-  return hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
-}
-
-olb_status olb_set_tile(olb_ctx* c, int32_t by) {
-  if (!c || (by != 8 && by != 16)) return OLB_E_ARG;
-  c->by = by;
-  return OLB_OK;
-}
-
+olb_status olb_set_tile(olb_ctx* c, int32_t by) { return c ? c->e.set_tile(by) : OLB_E_ARG; }
 olb_status olb_launch_counts(const olb_ctx* c, int32_t* stage, int32_t* walls) {
   if (!c || !stage || !walls) return OLB_E_ARG;
   *stage = 3;
-  *walls = c->g.walls ? 3 : 0;
+  *walls = c->e.walls ? 3 : 0;
   return OLB_OK;
 }
-
-const char* olb_last_error(const olb_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* olb_last_error(const olb_ctx* c) { return c ? c->e.err.c_str() : "null context"; }
+void olb_free(olb_ctx* c) { delete c; }
 
 const char* olb_strerror(olb_status s) {
   switch (s) {
@@ -355,6 +616,56 @@ const char* olb_strerror(olb_status s) {
   return "unknown status";
 }
 
-void olb_free(olb_ctx* c) { delete c; }
+// ----------------------------------------------------------------- batches --
+
+olb_status olb_batch_workspace_bytes(const olb_params* p, int32_t count, size_t* bytes) {
+  std::string why;
+  if (!bytes) return OLB_E_ARG;
+  olb_status s = validate_batch(p, count, why);
+  if (s) return s;
+  *bytes = engine_bytes(p, count);
+  return OLB_OK;
+}
+
+olb_status olb_batch_init(const olb_params* p, int32_t count, void* dev_workspace, size_t bytes,
+                          void* hip_stream, olb_batch** out) {
+  return make_engine(p, count, dev_workspace, bytes, hip_stream, out);
+}
+
+olb_status olb_batch_set_fields(olb_batch* b, int32_t i, const double* n, const double* ux,
+                                const double* uy, const double* T) {
+  return b ? b->e.set_fields(i, n, ux, uy, T) : OLB_E_ARG;
+}
+olb_status olb_batch_set_f(olb_batch* b, int32_t i, const double* f) {
+  return b ? b->e.set_f(i, f) : OLB_E_ARG;
+}
+olb_status olb_batch_get_f(olb_batch* b, int32_t i, double* f) { return b ? b->e.get_f(i, f) : OLB_E_ARG; }
+olb_status olb_batch_step(olb_batch* b, int32_t nsteps) { return b ? b->e.step(nsteps) : OLB_E_ARG; }
+olb_status olb_batch_sync(olb_batch* b) { return b ? b->e.read_flag() : OLB_E_ARG; }
+olb_status olb_batch_moments(olb_batch* b, int32_t i, double* n, double* ux, double* uy, double* T) {
+  return b ? b->e.moments(i, n, ux, uy, T) : OLB_E_ARG;
+}
+olb_status olb_batch_wall_density(olb_batch* b, int32_t i, double* lo, double* hi) {
+  return b ? b->e.wall_density(i, lo, hi) : OLB_E_ARG;
+}
+olb_status olb_batch_use_graph(olb_batch* b, int32_t steps_per_graph) {
+  if (!b || steps_per_graph < 0) return OLB_E_ARG;
+  b->e.drop_graph();
+  b->e.graph_steps = steps_per_graph == 0 ? 0 : 2 * ((steps_per_graph + 1) / 2);
+  return OLB_OK;
+}
+olb_status olb_batch_set_tile(olb_batch* b, int32_t by) { return b ? b->e.set_tile(by) : OLB_E_ARG; }
+olb_status olb_batch_autotune(olb_batch* b, int32_t trial_steps, const char* cache_path,
+                              int32_t* chosen_by) {
+  return b ? b->e.autotune(trial_steps, cache_path, chosen_by) : OLB_E_ARG;
+}
+olb_status olb_batch_tiles(const olb_batch* b, int32_t* tiles, int32_t* by) {
+  if (!b || !tiles || !by) return OLB_E_ARG;
+  *tiles = b->e.total_tiles;
+  *by = b->e.by;
+  return OLB_OK;
+}
+const char* olb_batch_last_error(const olb_batch* b) { return b ? b->e.err.c_str() : "null batch"; }
+void olb_batch_free(olb_batch* b) { delete b; }
 
 }  // extern "C"

@@ -67,6 +67,21 @@ _SIGS = {
     "olb_last_error": ([_vp], ctypes.c_char_p),
     "olb_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "olb_free": ([_vp], None),
+    "olb_batch_workspace_bytes": ([ctypes.POINTER(olb_params), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "olb_batch_init": ([ctypes.POINTER(olb_params), ctypes.c_int32, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "olb_batch_set_fields": ([_vp, ctypes.c_int32, _dp, _dp, _dp, _dp], ctypes.c_int),
+    "olb_batch_set_f": ([_vp, ctypes.c_int32, _dp], ctypes.c_int),
+    "olb_batch_get_f": ([_vp, ctypes.c_int32, _dp], ctypes.c_int),
+    "olb_batch_step": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "olb_batch_sync": ([_vp], ctypes.c_int),
+    "olb_batch_moments": ([_vp, ctypes.c_int32, _dp, _dp, _dp, _dp], ctypes.c_int),
+    "olb_batch_wall_density": ([_vp, ctypes.c_int32, _dp, _dp], ctypes.c_int),
+    "olb_batch_use_graph": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "olb_batch_set_tile": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "olb_batch_autotune": ([_vp, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "olb_batch_tiles": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "olb_batch_last_error": ([_vp], ctypes.c_char_p),
+    "olb_batch_free": ([_vp], None),
 }
 
 
@@ -90,9 +105,12 @@ def _ptr(a):
     return a.ctypes.data_as(_dp)
 
 
-def _check(rc, h=None):
+def _check(rc, h=None, batch=False):
     if rc != OLB_OK:
-        msg = lib().olb_last_error(h).decode() if h else lib().olb_strerror(rc).decode()
+        if h:
+            msg = (lib().olb_batch_last_error(h) if batch else lib().olb_last_error(h)).decode()
+        else:
+            msg = ""
         raise OlbError(rc, msg or lib().olb_strerror(rc).decode())
 
 
@@ -231,3 +249,160 @@ class Lattice:
 
     def launch_counts(self):
         return olb_launch_counts(self.h)
+
+
+# ------------------------------------------------------------------ batches --
+
+def _param_array(params_list):
+    arr = (olb_params * len(params_list))()
+    for i, p in enumerate(params_list):
+        arr[i] = make_params(p) if isinstance(p, dict) else p
+    return arr
+
+
+def olb_batch_workspace_bytes(params_list):
+    arr = _param_array(params_list)
+    n = ctypes.c_size_t()
+    _check(lib().olb_batch_workspace_bytes(arr, len(params_list), ctypes.byref(n)))
+    return int(n.value)
+
+
+def olb_batch_init(params_list, workspace_ptr, nbytes, stream_ptr):
+    arr = _param_array(params_list)
+    h = _vp()
+    _check(lib().olb_batch_init(arr, len(params_list), _vp(workspace_ptr), nbytes, _vp(stream_ptr),
+                                ctypes.byref(h)))
+    return h
+
+
+def olb_batch_set_fields(h, i, n, ux, uy, T):
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (n, ux, uy, T)]
+    _check(lib().olb_batch_set_fields(h, int(i), *(_ptr(a) for a in arrs)), h, True)
+
+
+def olb_batch_set_f(h, i, f):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    _check(lib().olb_batch_set_f(h, int(i), _ptr(f)), h, True)
+
+
+def olb_batch_get_f(h, i, shape):
+    f = np.empty((25,) + tuple(shape))
+    _check(lib().olb_batch_get_f(h, int(i), _ptr(f)), h, True)
+    return f
+
+
+def olb_batch_step(h, nsteps):
+    _check(lib().olb_batch_step(h, int(nsteps)), h, True)
+
+
+def olb_batch_sync(h):
+    _check(lib().olb_batch_sync(h), h, True)
+
+
+def olb_batch_moments(h, i, shape):
+    out = [np.empty(shape) for _ in range(4)]
+    _check(lib().olb_batch_moments(h, int(i), *(_ptr(a) for a in out)), h, True)
+    return tuple(out)
+
+
+def olb_batch_wall_density(h, i, nx):
+    lo, hi = np.empty(nx), np.empty(nx)
+    _check(lib().olb_batch_wall_density(h, int(i), _ptr(lo), _ptr(hi)), h, True)
+    return lo, hi
+
+
+def olb_batch_use_graph(h, steps_per_graph):
+    _check(lib().olb_batch_use_graph(h, int(steps_per_graph)), h, True)
+
+
+def olb_batch_set_tile(h, by):
+    _check(lib().olb_batch_set_tile(h, int(by)), h, True)
+
+
+def olb_batch_autotune(h, trial_steps, cache_path=None):
+    chosen = ctypes.c_int32()
+    path = cache_path.encode() if cache_path else None
+    _check(lib().olb_batch_autotune(h, int(trial_steps), path, ctypes.byref(chosen)), h, True)
+    return chosen.value
+
+
+def olb_batch_tiles(h):
+    t, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().olb_batch_tiles(h, ctypes.byref(t), ctypes.byref(b)), h, True)
+    return t.value, b.value
+
+
+def olb_batch_free(h):
+    lib().olb_batch_free(h)
+
+
+class Batch:
+    """Many instances on ``device``, stepped in lockstep by single launches.
+    Uses its own (default-priority) stream so that HIP graphs can be captured."""
+
+    def __init__(self, params_list, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the D2Q25 library has no CPU path")
+        self.params = []
+        for p in params_list:
+            full = dict(_DEFAULTS)
+            full.update(p)
+            self.params.append(full)
+        self.device = torch.device(device)
+        nbytes = olb_batch_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.h = olb_batch_init(self.params, aligned, nbytes, self.stream.cuda_stream)
+        self.nbytes = nbytes
+
+    def __len__(self):
+        return len(self.params)
+
+    def shape(self, i):
+        return (int(self.params[i]["ny"]), int(self.params[i]["nx"]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            olb_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_fields(self, i, n, ux, uy, T):
+        olb_batch_set_fields(self.h, i, n, ux, uy, T)
+
+    def set_f(self, i, f):
+        olb_batch_set_f(self.h, i, f)
+
+    def get_f(self, i):
+        return olb_batch_get_f(self.h, i, self.shape(i))
+
+    def step(self, nsteps=1):
+        olb_batch_step(self.h, nsteps)
+
+    def sync(self):
+        olb_batch_sync(self.h)
+
+    def moments(self, i):
+        return olb_batch_moments(self.h, i, self.shape(i))
+
+    def wall_density(self, i):
+        return olb_batch_wall_density(self.h, i, self.shape(i)[1])
+
+    def use_graph(self, steps_per_graph):
+        olb_batch_use_graph(self.h, steps_per_graph)
+
+    def set_tile(self, by):
+        olb_batch_set_tile(self.h, by)
+
+    def autotune(self, trial_steps=3, cache_path=None):
+        return olb_batch_autotune(self.h, trial_steps, cache_path)
+
+    def tiles(self):
+        return olb_batch_tiles(self.h)

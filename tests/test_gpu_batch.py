@@ -1,0 +1,165 @@
+"""Batched instances: one stage launch covers every instance's tiles.
+
+Checks per-instance parity with the oracle, bitwise equality with separate
+single-instance runs, HIP-graph replays against eager launches (several
+replays with eager work and synchronisation in between), and the autotuner.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import olb_inputs as I
+import oracle
+from _metrics import moment_errors, rel_scalar
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+
+def _olb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_1702_01690_amd import olb
+    return olb
+
+
+def _channels(precision=0):
+    cases = [I.channel(70, 20, tw=0.75 * I.T_CRIT, seed=11),
+             I.channel(40, 33, tw=0.90 * I.T_CRIT, seed=12),
+             I.channel(129, 12, tw=0.80 * I.T_CRIT, seed=13)]
+    for c in cases:
+        c.params["precision"] = precision
+        c.params["rho_ref"] = I.N_CRIT
+    return cases
+
+
+def _periodic():
+    a = I.shear32()
+    b = I.spinodal(66, 45, seed=21)
+    b.params["ds"] = a.params["ds"]     # instances may differ in every parameter
+    return [a, b]
+
+
+def _oracle_run(case, steps):
+    o = oracle.Oracle(case.params)
+    o.set_fields(*case.fields)
+    o.step(steps)
+    return o.moments()
+
+
+def _batch(cases, graph=0, by=None):
+    olb = _olb()
+    b = olb.Batch([c.params for c in cases])
+    if by:
+        b.set_tile(by)
+    if graph:
+        b.use_graph(graph)
+    for i, c in enumerate(cases):
+        b.set_fields(i, *c.fields)
+    return b
+
+
+@pytest.mark.parametrize("kind", ["walls", "periodic"])
+def test_batch_fp64_matches_oracle_per_instance(kind):
+    cases = _channels() if kind == "walls" else _periodic()
+    steps = 20
+    print(f"[batch] {kind}: {[c.name for c in cases]} steps={steps}", flush=True)
+    b = _batch(cases)
+    b.step(steps)
+    b.sync()
+    for i, c in enumerate(cases):
+        err = moment_errors(b.moments(i), _oracle_run(c, steps))
+        print(f"[batch] {c.name}: {err}", flush=True)
+        assert max(err.values()) < TOL64, (c.name, err)
+
+
+def test_batch_equals_single_instance_runs_bitwise():
+    olb = _olb()
+    cases = _channels()
+    b = _batch(cases)
+    b.step(7)
+    for i, c in enumerate(cases):
+        lat = olb.Lattice(c.params)
+        lat.set_fields(*c.fields)
+        lat.step(7)
+        np.testing.assert_array_equal(b.get_f(i), lat.get_f())
+        lo, hi = lat.wall_density()
+        blo, bhi = b.wall_density(i)
+        np.testing.assert_array_equal(blo, lo)
+        np.testing.assert_array_equal(bhi, hi)
+
+
+@pytest.mark.parametrize("by", [8, 16])
+def test_graph_replays_match_eager_launches(by):
+    cases = _channels()
+    g = _batch(cases, graph=2, by=by)
+    e = _batch(cases, by=by)
+    for rnd, steps in enumerate((4, 3, 6)):
+        g.step(steps)          # graph replays (+ one direct step when odd)
+        e.step(steps)
+        g.sync()
+        e.sync()
+        for i in range(len(cases)):
+            # eager work between replays: read-outs through other kernels
+            gm, em = g.moments(i), e.moments(i)
+            for a, bb in zip(gm, em):
+                np.testing.assert_array_equal(a, bb)
+        print(f"[batch] graph round {rnd} ({steps} steps) bitwise equal", flush=True)
+    np.testing.assert_array_equal(g.get_f(1), e.get_f(1))
+
+
+def test_autotune_picks_a_tile_and_caches_it(tmp_path):
+    olb = _olb()
+    cases = _channels()
+    cache = str(tmp_path / "tune.json")
+    b = olb.Batch([c.params for c in cases])
+    by = b.autotune(trial_steps=2, cache_path=cache)
+    assert by in (8, 16)
+    data = json.load(open(cache))
+    key = next(iter(data))
+    assert data[key]["by"] == by and data[key]["ms_per_step_by8"] > 0
+    # the trial discarded the state: stepping now is an error
+    with pytest.raises(olb.OlbError) as e:
+        b.step(1)
+    assert e.value.code == olb.OLB_E_STATE
+    # a second batch of the same shape reads the cache
+    b2 = olb.Batch([c.params for c in cases])
+    assert b2.autotune(trial_steps=2, cache_path=cache) == by
+    assert b2.tiles()[1] == by
+    for i, c in enumerate(cases):
+        b.set_fields(i, *c.fields)
+    b.step(5)
+    ref = _batch(cases, by=by)
+    ref.step(5)
+    np.testing.assert_array_equal(b.get_f(0), ref.get_f(0))
+
+
+def test_batch_fp32_mixed_density_within_1e5():
+    cases = _channels(precision=1)
+    steps = 10
+    b = _batch(cases)
+    b.step(steps)
+    for i, c in enumerate(cases):
+        p64 = dict(c.params)
+        p64["precision"] = 0
+        c64 = I.Case(c.name, p64, c.n, c.ux, c.uy, c.T, steps)
+        err = moment_errors(b.moments(i), _oracle_run(c64, steps))
+        print(f"[batch] fp32 {c.name}: {err}", flush=True)
+        assert err["n"] < 1e-5, err
+
+
+def test_batch_rejects_mixed_kinds_and_bad_index():
+    olb = _olb()
+    a = I.shear32().params
+    w = I.channel(16, 8).params
+    with pytest.raises(olb.OlbError) as e:
+        olb.Batch([a, w])
+    assert e.value.code == olb.OLB_E_ARG
+    b = olb.Batch([a])
+    with pytest.raises(olb.OlbError) as e:
+        b.set_fields(3, *I.shear32().fields)
+    assert e.value.code == olb.OLB_E_ARG

@@ -37,7 +37,7 @@ ALG_FLOPS_PER_CELL_STAGE = 4230
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("olb_kernels.hip", "olb_consts.hpp", "olb_device.hpp"):
+    for name in ("olb_kernels.hip", "olb_consts.hpp", "olb_device.hpp", "olb_feq.hpp"):
         with open(os.path.join(ROOT, "paper_1702_01690_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -94,6 +94,11 @@ olb_status olb_init(const olb_params* p, void* dev_workspace, size_t bytes,
 olb_status olb_set_fields(olb_ctx* c, const double* n, const double* ux,
                           const double* uy, const double* T);
 
+/* Same from device double fields [4][ny][nx] (n, u_x, u_y, T planes), e.g.
+ * restricted moments of a finer run.  The fields are checked on the device
+ * first (OLB_E_DOMAIN leaves the previous state).  Synchronous. */
+olb_status olb_set_fields_device(olb_ctx* c, const double* dev_fields);
+
 /* Advance nsteps full RK-3 steps (Eq. rk3), each of three stages computing
  * L[f] of Eq. ecast: moments, EOS, 49-point force, force term of Eq. derf,
  * Hermite equilibrium, BGK, WENO-5 fluxes in x and y, wall ghosts
@@ -152,12 +157,15 @@ olb_status olb_batch_init(const olb_params* p, int32_t count, void* dev_workspac
                           void* hip_stream, olb_batch** out);
 olb_status olb_batch_set_fields(olb_batch* b, int32_t i, const double* n, const double* ux,
                                 const double* uy, const double* T);
+olb_status olb_batch_set_fields_device(olb_batch* b, int32_t i, const double* dev_fields);
 olb_status olb_batch_set_f(olb_batch* b, int32_t i, const double* f);
 olb_status olb_batch_get_f(olb_batch* b, int32_t i, double* f);
 /* nsteps RK-3 steps of every instance (all must have f).  Asynchronous. */
 olb_status olb_batch_step(olb_batch* b, int32_t nsteps);
 olb_status olb_batch_sync(olb_batch* b);
 olb_status olb_batch_moments(olb_batch* b, int32_t i, double* n, double* ux, double* uy, double* T);
+/* Moments of instance i into a device buffer of 4 * nx * ny doubles.  Async. */
+olb_status olb_batch_moments_device(olb_batch* b, int32_t i, double* dev_out);
 olb_status olb_batch_wall_density(olb_batch* b, int32_t i, double* nw_lo, double* nw_hi);
 /* Replay olb_batch_step in HIP graphs of steps_per_graph RK-3 steps (rounded
  * up to even; 0 = direct launches).  Captured on first use; needs a
@@ -174,6 +182,74 @@ olb_status olb_batch_autotune(olb_batch* b, int32_t trial_steps, const char* cac
 olb_status olb_batch_tiles(const olb_batch* b, int32_t* tiles, int32_t* by);
 const char* olb_batch_last_error(const olb_batch* b);
 void olb_batch_free(olb_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Learned closure on a coarse lattice.  Neither the network nor its training
+ * comes from the paper: it is an extension that corrects a 4x-coarser run of
+ * the same method towards the restriction of a fine run.
+ *
+ * Network: moments (n, u_x, u_y, T) -> conv3x3(4->32) -> ReLU ->
+ * conv3x3(32->32) -> ReLU -> conv3x3(32->4) -> correction (dn, du_x, du_y,
+ * dT), periodic padding.  Inputs are normalised (m - in_mean) / in_scale,
+ * outputs scaled by out_scale.  Convolutions run on the bf16 matrix cores
+ * with FP32 accumulation; activations and back-propagated gradients are
+ * rounded to bf16 (nearest even) between layers; parameters, gradients and
+ * Adam moments are FP32.
+ *
+ * Parameters: one FP32 vector of OLB_CLOSURE_NPARAM values
+ *   [W1 (32x4x3x3) | b1 (32) | W2 (32x32x3x3) | b2 (32) | W3 (4x32x3x3) | b3 (4)]
+ * with W[co][ci][ky][kx] weighting input (x + kx - 1, y + ky - 1).
+ *
+ * Moment planes are device double [4][ny][nx] (n, u_x, u_y, T), y outer.
+ * A closure object holds no device memory of its own: the caller's
+ * workspace (256-byte aligned, olb_closure_workspace_bytes) keeps
+ * activations, parameters, gradients and Adam state.  Work is enqueued on
+ * hip_stream; calls that return host values synchronise it.
+ * ------------------------------------------------------------------------ */
+#define OLB_CLOSURE_NPARAM 11588
+typedef struct olb_closure olb_closure;
+
+olb_status olb_closure_workspace_bytes(int32_t nx, int32_t ny, size_t* bytes);
+olb_status olb_closure_init(int32_t nx, int32_t ny, void* dev_workspace, size_t bytes,
+                            void* hip_stream, olb_closure** out);
+/* Input normalisation and output scale, 4 values each (scales > 0). */
+olb_status olb_closure_set_norm(olb_closure* c, const double in_mean[4], const double in_scale[4],
+                                const double out_scale[4]);
+/* Host FP32 parameters in / out; set_params also resets the Adam state.
+ * Non-finite parameters: OLB_E_ARG. */
+olb_status olb_closure_set_params(olb_closure* c, const float* params);
+olb_status olb_closure_get_params(olb_closure* c, float* params);
+/* Network output for device moments [4][ny][nx] -> device corrections
+ * [4][ny][nx] (double).  Asynchronous.  OLB_E_STATE before set_params. */
+olb_status olb_closure_forward(olb_closure* c, const double* dev_moments, double* dev_delta);
+/* Training pair: dev_moments (the coarse run's moments, the network input)
+ * and dev_reference (the restricted fine moments at the same time), both
+ * device [4][ny][nx].  Loss L = mean over nodes and the 4 channels of
+ * (out - (reference - moments) / out_scale)^2 with out the normalised network
+ * output; grad = dL/dparams (host FP32, OLB_CLOSURE_NPARAM values; loss may
+ * be NULL).  Synchronous. */
+olb_status olb_closure_gradients(olb_closure* c, const double* dev_moments, const double* dev_reference,
+                                 float* grad, float* loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on that
+ * loss with learning rate lr.  loss may be NULL (then asynchronous). */
+olb_status olb_closure_train_step(olb_closure* c, const double* dev_moments, const double* dev_reference,
+                                  float lr, float* loss);
+/* Correct a single-instance coarse lattice of the closure's size in place:
+ * m = moments of f^n, dm = network(m), f <- f + f^eq(m + dm) - f^eq(m) at
+ * every node where m + dm is admissible (finite, 0 < n < 1/b, T > 0); other
+ * nodes are left as they are and counted in *skipped (may be NULL).  The
+ * lattice's carried state is refreshed.  Synchronises both streams when the
+ * lattice runs on another stream. */
+olb_status olb_closure_apply(olb_closure* c, olb_ctx* coarse, int32_t* skipped);
+const char* olb_closure_last_error(const olb_closure* c);
+void olb_closure_free(olb_closure* c);
+
+/* Conservative restriction of fine moment planes [4][fny][fnx] to coarse
+ * planes [4][fny/factor][fnx/factor]: n, n u and n (u^2 + 2T) (m = 1, D = 2)
+ * are averaged over factor x factor blocks, then u and T recovered.  Both
+ * device double; fnx, fny multiples of factor.  Asynchronous on hip_stream. */
+olb_status olb_restrict(const double* dev_fine, int32_t fnx, int32_t fny, int32_t factor,
+                        double* dev_coarse, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -183,3 +183,61 @@ def random_f_perturbation(seed: int, shape, amplitude: float) -> np.ndarray:
     """Seeded multiplicative noise (1 + amplitude (2U - 1)) for raw f tests."""
     U = uniform(seed, int(np.prod(shape))).reshape(shape)
     return 1.0 + amplitude * (2.0 * U - 1.0)
+
+
+# ---------------------------------------------------------- learned closure --
+# Fine spinodal samples at T = (0.75 + 0.2 U) T_c, their 4x-coarser
+# counterparts (same physical domain and time: ds and dt four times larger),
+# random network parameters and random coarse moment fields.
+
+CLOSURE_FACTOR = 4
+CLOSURE_PARAM_SHAPES = ((32, 4, 3, 3), (32,), (32, 32, 3, 3), (32,), (4, 32, 3, 3), (4,))
+
+
+def closure_sample(nx=2048, ny=None, seed=5000, ds=1.0 / 320, dt=2e-4, tau=0.005, noise=0.01):
+    """Fine spinodal sample: the first draw of the seed's stream sets T, the
+    next nx * ny ones the density noise n = 3.5 (1 + noise (2U - 1)); u = 0."""
+    ny = nx if ny is None else ny
+    U = uniform(seed, 1 + nx * ny)
+    temperature = (0.75 + 0.2 * U[0]) * T_CRIT
+    n = N_CRIT * (1.0 + noise * (2.0 * U[1:].reshape(ny, nx) - 1.0))
+    z = np.zeros((ny, nx))
+    p = _params(nx, ny, ds, dt, tau)
+    return Case(f"closure{nx}x{ny}s{seed}", p, n, z, z.copy(), np.full((ny, nx), temperature), 0)
+
+
+def coarse_params(fine_params, factor=CLOSURE_FACTOR, precision=1):
+    """Parameters of the factor-times coarser lattice over the same domain."""
+    p = dict(fine_params)
+    p["nx"] = fine_params["nx"] // factor
+    p["ny"] = fine_params["ny"] // factor
+    p["ds"] = fine_params["ds"] * factor
+    p["dt"] = fine_params["dt"] * factor
+    p["precision"] = precision
+    p["rho_ref"] = N_CRIT
+    return p
+
+
+def closure_params(seed=7, last_scale=0.1) -> np.ndarray:
+    """Random float32 parameter vector: weights uniform in +-sqrt(6 / fan_in)
+    (fan_in = 9 C_in), the last layer's scaled by last_scale, biases zero."""
+    out = []
+    draws = uniform(seed, sum(int(np.prod(s)) for s in CLOSURE_PARAM_SHAPES))
+    o = 0
+    for i, shape in enumerate(CLOSURE_PARAM_SHAPES):
+        size = int(np.prod(shape))
+        if len(shape) == 4:
+            bound = np.sqrt(6.0 / (9 * shape[1])) * (last_scale if i == 4 else 1.0)
+            out.append(bound * (2.0 * draws[o:o + size] - 1.0))
+        else:
+            out.append(np.zeros(size))
+        o += size
+    return np.concatenate(out).astype(np.float32)
+
+
+def closure_moments(nx, ny, seed=11, amplitude=0.01) -> np.ndarray:
+    """Random admissible moment planes (4, ny, nx) near the spinodal state:
+    n = 3.5 (1 + a (2U - 1)), u = a (2U - 1), T = 0.85 T_c (1 + a (2U - 1))."""
+    U = 2.0 * uniform(seed, 4 * nx * ny).reshape(4, ny, nx) - 1.0
+    return np.stack([N_CRIT * (1.0 + amplitude * U[0]), amplitude * U[1], amplitude * U[2],
+                     0.85 * T_CRIT * (1.0 + amplitude * U[3])])

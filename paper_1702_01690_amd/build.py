@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libolb.so")
-SOURCES = ["olb_kernels.hip", "olb_runtime.hip"]
+SOURCES = ["olb_kernels.hip", "olb_runtime.hip", "olb_closure.hip"]
 ARCH = os.environ.get("OLB_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",

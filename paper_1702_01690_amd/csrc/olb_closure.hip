@@ -1,0 +1,705 @@
+// olb_closure.hip -- learned coarse-grid closure on gfx950.
+//
+// A 3-layer convolutional network (3x3 kernels, periodic padding, 4 -> 32 ->
+// 32 -> 4 channels, ReLU between layers) maps the moments (n, u_x, u_y, T) of
+// a coarse lattice to a correction of those moments.  Every convolution is an
+// implicit GEMM on the bf16 matrix cores (v_mfma_f32_16x16x16_bf16, FP32
+// accumulate): forward, backward-data (fused with the ReLU mask) and
+// backward-weight (pixel reduction, FP32 atomics).  Master weights, Adam
+// moments and gradients are FP32; activations and gradients entering the
+// matrix cores are rounded to bf16 (round to nearest even).
+//
+// Layouts: activations [pixel][channel], pixel = y * nx + x; parameters are
+// one FP32 vector [W1 | b1 | W2 | b2 | W3 | b3] with W[co][ci][ky][kx];
+// bf16 weight matrices Wt[co][k] with k = tap * Cin + ci, tap = 3 ky + kx,
+// rows padded to 16 and k padded to a multiple of 16.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/olb.h"
+#include "olb_consts.hpp"
+#include "olb_device.hpp"
+#include "olb_feq.hpp"
+
+namespace olbk {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16;
+
+__device__ __forceinline__ bf16 to_bf16(float f) {
+  // round to nearest even (finite inputs)
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (bf16)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(bf16 h) { return __uint_as_float(((unsigned)h) << 16); }
+
+// offsets of the 9 taps (tap = 3 ky + kx, neighbour (x + kx - 1, y + ky - 1))
+__device__ __forceinline__ int tap_pixel(int p, int tap, int nx, int ny) {
+  const int y = p / nx, x = p - y * nx;
+  int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+  yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+  xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+  return yy * nx + xx;
+}
+
+constexpr int kp_of(int cin) { return (9 * cin + 15) / 16 * 16; }
+
+// ---------------------------------------------------------------- forward --
+// Z[p][co] = b[co] + sum_k Wt[co][k] X[p + off(tap)][ci];  A = bf16(relu(Z)).
+// One wave computes 16 pixels x all output channels.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) conv_fwd(const bf16* __restrict__ X, const bf16* __restrict__ Wt,
+                                                const float* __restrict__ bias, float* __restrict__ Z,
+                                                bf16* __restrict__ A, int nx, int ny, int relu) {
+  constexpr int K = 9 * CIN, KP = kp_of(CIN), NT = (COUT + 15) / 16;
+  const int P = nx * ny;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p0 = (blockIdx.x * 4 + wave) * 16;
+  if (p0 >= P) return;
+  const int i = lane & 15, g = lane >> 4;
+  const int pa = min(p0 + i, P - 1);  // A-operand row (pixel)
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KP / 16; ++ks) {
+    bf16x4 a;
+    const int k0 = ks * 16 + 4 * g;  // 4 consecutive k share a tap (CIN % 4 == 0)
+    if (k0 < K) {
+      const int tap = k0 / CIN, ci = k0 - tap * CIN;
+      const bf16* src = X + (size_t)tap_pixel(pa, tap, nx, ny) * CIN + ci;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[v] = (short)src[v];
+    } else {
+      a = bf16x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      bf16x4 b;
+      const bf16* w = Wt + (size_t)(t * 16 + i) * KP + k0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = (short)w[v];
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+    }
+  }
+  // lane holds D[4g + v][i]: pixel p0 + 4g + v, channel t * 16 + i
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = t * 16 + i;
+    if (co >= COUT) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int p = p0 + 4 * g + v;
+      if (p >= P) continue;
+      const float z = acc[t][v] + bias[co];
+      Z[(size_t)p * COUT + co] = z;
+      A[(size_t)p * COUT + co] = to_bf16(relu ? fmaxf(z, 0.f) : z);
+    }
+  }
+}
+
+// ----------------------------------------------------------- backward data --
+// dX[q][ci] = sum_{tap, co} G[q - off(tap)][co] Wt[co][tap * CIN + ci]; the
+// result is multiplied by the ReLU mask (Zprev > 0) of the layer below and
+// rounded to bf16: the gradient with respect to that layer's pre-activation.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) conv_bwd_data(const bf16* __restrict__ G, const bf16* __restrict__ Wt,
+                                                     const float* __restrict__ Zprev,
+                                                     bf16* __restrict__ Gprev, int nx, int ny) {
+  constexpr int K = 9 * COUT, KP = (K + 15) / 16 * 16, NT = (CIN + 15) / 16;
+  constexpr int WKP = kp_of(CIN);
+  const int P = nx * ny;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q0 = (blockIdx.x * 4 + wave) * 16;
+  if (q0 >= P) return;
+  const int i = lane & 15, g = lane >> 4;
+  const int qa = min(q0 + i, P - 1);
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KP / 16; ++ks) {
+    const int k0 = ks * 16 + 4 * g;  // k = tap * COUT + co
+    bf16x4 a;
+    if (k0 < K) {
+      const int tap = k0 / COUT, co = k0 - tap * COUT;
+      // neighbour q - off(tap): the tap mirrored through the centre
+      const bf16* src = G + (size_t)tap_pixel(qa, 8 - tap, nx, ny) * COUT + co;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[v] = (short)src[v];
+    } else {
+      a = bf16x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      bf16x4 b;
+      const int ci = t * 16 + i;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = k0 + v;
+        if (k < K && ci < CIN) {
+          const int tap = k / COUT, co = k - tap * COUT;
+          b[v] = (short)Wt[(size_t)co * WKP + tap * CIN + ci];
+        } else {
+          b[v] = 0;
+        }
+      }
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int ci = t * 16 + i;
+    if (ci >= CIN) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = q0 + 4 * g + v;
+      if (q >= P) continue;
+      const size_t o = (size_t)q * CIN + ci;
+      Gprev[o] = to_bf16(Zprev[o] > 0.f ? acc[t][v] : 0.f);
+    }
+  }
+}
+
+// --------------------------------------------------------- backward weight --
+// dW[co][ci][tap] += sum_p G[p][co] X[p + off(tap)][ci]  (GEMM M = COUT,
+// N = 9 CIN, reduction over a chunk of pixels per workgroup; the output
+// tiles are shared out among the 4 waves; FP32 atomics add the partial sums).
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) conv_bwd_weight(const bf16* __restrict__ G, const bf16* __restrict__ X,
+                                                       float* __restrict__ dW, int nx, int ny, int chunk) {
+  constexpr int K = 9 * CIN, KP = kp_of(CIN), MT = (COUT + 15) / 16, NTK = KP / 16;
+  constexpr int TILES = MT * NTK, PER = (TILES + 3) / 4;
+  const int P = nx * ny;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int pbeg = blockIdx.x * chunk, pend = min(pbeg + chunk, P);
+  f32x4 acc[PER];
+#pragma unroll
+  for (int s = 0; s < PER; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int p0 = pbeg; p0 < pend; p0 += 16) {
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int tile = wave * PER + s;
+      if (tile >= TILES) continue;
+      const int mt = tile / NTK, nt = tile - mt * NTK;
+      bf16x4 a, b;
+      const int co = mt * 16 + i;
+      const int k = nt * 16 + i;
+      const int tap = k / CIN, ci = k - tap * CIN;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = p0 + 4 * g + v;
+        const bool ok = p < pend;
+        a[v] = (ok && co < COUT) ? (short)G[(size_t)p * COUT + co] : (short)0;
+        b[v] = (ok && k < K) ? (short)X[(size_t)tap_pixel(p, tap, nx, ny) * CIN + ci] : (short)0;
+      }
+      acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[s], 0, 0, 0);
+    }
+  }
+  // lane holds D[4g + v][i]: output channel mt*16 + 4g + v, k = nt*16 + i
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int tile = wave * PER + s;
+    if (tile >= TILES) continue;
+    const int mt = tile / NTK, nt = tile - mt * NTK;
+    const int k = nt * 16 + i;
+    if (k >= K) continue;
+    const int tap = k / CIN, ci = k - tap * CIN;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int co = mt * 16 + 4 * g + v;
+      if (co < COUT) atomicAdd(&dW[((size_t)co * CIN + ci) * 9 + tap], acc[s][v]);
+    }
+  }
+}
+
+// db[c] += sum_p G[p][c]
+template <int C>
+__global__ void __launch_bounds__(256) bias_grad(const bf16* __restrict__ G, float* __restrict__ db, int P) {
+  __shared__ float part[256];
+  float s[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) s[c] = 0.f;
+  for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256)
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c] += from_bf16(G[(size_t)p * C + c]);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    part[threadIdx.x] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&db[c], part[0]);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ glue kernels --
+
+// Conservative restriction r x r: density, momentum and energy densities are
+// averaged, then (n, u, T) recovered (m = 1, D = 2).
+__global__ void restrict_kernel(const double* __restrict__ fine, int fnx, int fny, int r,
+                                double* __restrict__ coarse) {
+  const int cnx = fnx / r, cny = fny / r;
+  const int X = blockIdx.x * blockDim.x + threadIdx.x, Y = blockIdx.y;
+  if (X >= cnx || Y >= cny) return;
+  const size_t FN = (size_t)fnx * fny, CN = (size_t)cnx * cny;
+  double n = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+  for (int dy = 0; dy < r; ++dy)
+    for (int dx = 0; dx < r; ++dx) {
+      const size_t m = (size_t)(Y * r + dy) * fnx + (X * r + dx);
+      const double nn = fine[m], ux = fine[FN + m], uy = fine[2 * FN + m], T = fine[3 * FN + m];
+      n += nn;
+      jx += nn * ux;
+      jy += nn * uy;
+      e += nn * (ux * ux + uy * uy + 2.0 * T);
+    }
+  const double inv = 1.0 / (r * r);
+  n *= inv;
+  jx *= inv;
+  jy *= inv;
+  e *= inv;
+  const size_t c = (size_t)Y * cnx + X;
+  const double ux = jx / n, uy = jy / n;
+  coarse[c] = n;
+  coarse[CN + c] = ux;
+  coarse[2 * CN + c] = uy;
+  coarse[3 * CN + c] = 0.5 * (e / n - ux * ux - uy * uy);
+}
+
+struct Norm {
+  float in_mean[4], in_inv_scale[4], out_scale[4];
+};
+
+// moment planes (FP64) -> normalised bf16 input [p][4]
+__global__ void prep_kernel(const double* __restrict__ m, int P, Norm nm, bf16* __restrict__ x) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    x[(size_t)p * 4 + c] = to_bf16((float)((m[(size_t)c * P + p] - nm.in_mean[c]) * nm.in_inv_scale[c]));
+}
+
+// MSE loss on the normalised correction, whose target is (reference - m) /
+// out_scale; G3 = dL/dZ3 (bf16), loss accumulated
+__global__ void loss_kernel(const float* __restrict__ Z3, const double* __restrict__ m,
+                            const double* __restrict__ ref, int P, Norm nm, bf16* __restrict__ G3,
+                            float* __restrict__ loss) {
+  __shared__ float part[256];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (p < P) {
+    const float scale = 2.0f / (4.0f * (float)P);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const size_t o = (size_t)c * P + p;
+      const float t = (float)((ref[o] - m[o]) / nm.out_scale[c]);
+      const float d = Z3[(size_t)p * 4 + c] - t;
+      l += d * d;
+      G3[(size_t)p * 4 + c] = to_bf16(scale * d);
+    }
+  }
+  part[threadIdx.x] = l;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, part[0] / (4.0f * (float)P));
+}
+
+// FP32 master parameters -> bf16 weight matrices (padded) of the three layers
+__global__ void pack_weights(const float* __restrict__ w, bf16* __restrict__ W1, bf16* __restrict__ W2,
+                             bf16* __restrict__ W3) {
+  // layer l: Cin, Cout, offset of W in the flat vector
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int KP1 = kp_of(4), KP2 = kp_of(32), KP3 = kp_of(32);
+  constexpr int N1 = 32 * KP1, N2 = 32 * KP2, N3 = 16 * KP3;
+  constexpr int O1 = 0, O2 = 32 * 4 * 9 + 32, O3 = O2 + 32 * 32 * 9 + 32;
+  if (idx < N1) {
+    const int co = idx / KP1, k = idx - co * KP1;
+    float v = 0.f;
+    if (k < 9 * 4) v = w[O1 + (co * 4 + k % 4) * 9 + k / 4];
+    W1[idx] = to_bf16(v);
+  } else if (idx < N1 + N2) {
+    const int j = idx - N1, co = j / KP2, k = j - co * KP2;
+    float v = 0.f;
+    if (k < 9 * 32) v = w[O2 + (co * 32 + k % 32) * 9 + k / 32];
+    W2[j] = to_bf16(v);
+  } else if (idx < N1 + N2 + N3) {
+    const int j = idx - N1 - N2, co = j / KP3, k = j - co * KP3;
+    float v = 0.f;
+    if (co < 4 && k < 9 * 32) v = w[O3 + (co * 32 + k % 32) * 9 + k / 32];
+    W3[j] = to_bf16(v);
+  }
+}
+
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int n, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// network output (normalised) -> correction planes (FP64)
+__global__ void delta_kernel(const float* __restrict__ Z3, int P, Norm nm, double* __restrict__ delta) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) delta[(size_t)c * P + p] = (double)Z3[(size_t)p * 4 + c] * nm.out_scale[c];
+}
+
+// f <- f + f^eq(m + dm) - f^eq(m) where the corrected moments are admissible
+// (finite, 0 < n < 1/b, T > 0); other nodes keep f (counted in skipped).
+template <typename Real>
+__global__ void apply_kernel(const double* __restrict__ m, const double* __restrict__ dm, Geometry geo,
+                             Real* __restrict__ f, double b, int* __restrict__ skipped) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= geo.nx) return;
+  const size_t N = (size_t)geo.nx * geo.ny, c = (size_t)y * geo.nx + x;
+  const double n0 = m[c], ux0 = m[N + c], uy0 = m[2 * N + c], T0 = m[3 * N + c];
+  const double n1 = n0 + dm[c], ux1 = ux0 + dm[N + c], uy1 = uy0 + dm[2 * N + c], T1 = T0 + dm[3 * N + c];
+  const bool ok = isfinite(n1) && isfinite(ux1) && isfinite(uy1) && isfinite(T1) && n1 > 0.0 &&
+                  (b <= 0.0 || n1 * b < 1.0) && T1 > 0.0;
+  if (!ok) {
+    atomicAdd(skipped, 1);
+    return;
+  }
+  double h0x[5], h0y[5], h1x[5], h1y[5];
+  hfac(ux0, T0 - 1.0, h0x);
+  hfac(uy0, T0 - 1.0, h0y);
+  hfac(ux1, T1 - 1.0, h1x);
+  hfac(uy1, T1 - 1.0, h1y);
+  const int own = (y + 3) * geo.nx + x;
+#pragma unroll
+  for (int ky = 0; ky < 5; ++ky)
+#pragma unroll
+    for (int kx = 0; kx < 5; ++kx) {
+      const double w = Wk[kx] * Wk[ky];
+      const double d = w * (n1 * (1.0 + h1x[kx]) * (1.0 + h1y[ky]) - n0 * (1.0 + h0x[kx]) * (1.0 + h0y[ky]));
+      Real* q = f + (5 * ky + kx) * geo.ps + own;
+      *q = (Real)((double)*q + d);
+    }
+}
+
+}  // namespace olbk
+
+// --------------------------------------------------------------------------
+// host side
+// --------------------------------------------------------------------------
+
+
+namespace {
+constexpr int NPARAM = 32 * 4 * 9 + 32 + 32 * 32 * 9 + 32 + 4 * 32 * 9 + 4;
+static_assert(NPARAM == OLB_CLOSURE_NPARAM, "parameter count");
+constexpr size_t AL = 256;
+size_t al(size_t v) { return (v + AL - 1) / AL * AL; }
+
+struct CLayout {
+  size_t x0, z1, a1, z2, a2, z3, g3, g2, g1, mom, delta, par, grad, am, av, w1, w2, w3, loss, skip, total;
+};
+
+CLayout clayout(int nx, int ny) {
+  const size_t P = (size_t)nx * ny;
+  CLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += al(bytes); return r; };
+  L.x0 = take(P * 4 * 2);
+  L.z1 = take(P * 32 * 4);
+  L.a1 = take(P * 32 * 2);
+  L.z2 = take(P * 32 * 4);
+  L.a2 = take(P * 32 * 2);
+  L.z3 = take(P * 4 * 4);
+  L.g3 = take(P * 4 * 2);
+  L.g2 = take(P * 32 * 2);
+  L.g1 = take(P * 32 * 2);
+  L.mom = take(P * 4 * 8);
+  L.delta = take(P * 4 * 8);
+  L.par = take(NPARAM * 4);
+  L.grad = take(NPARAM * 4);
+  L.am = take(NPARAM * 4);
+  L.av = take(NPARAM * 4);
+  L.w1 = take(32 * olbk::kp_of(4) * 2);
+  L.w2 = take(32 * olbk::kp_of(32) * 2);
+  L.w3 = take(16 * olbk::kp_of(32) * 2);
+  L.loss = take(4);
+  L.skip = take(4);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+struct olb_closure {
+  int nx, ny, P;
+  hipStream_t stream;
+  unsigned char* ws;
+  CLayout L;
+  olbk::Norm norm;
+  int adam_t = 0;
+  bool have_params = false;
+  std::string err;
+
+  template <typename T>
+  T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+
+  olb_status hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return OLB_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return OLB_E_DEVICE;
+  }
+
+  int pix_blocks() const { return (P + 63) / 64; }  // 4 waves x 16 pixels
+
+  olb_status forward(const double* dev_m) {
+    using namespace olbk;
+    hipLaunchKernelGGL(prep_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, dev_m, P, norm, at<bf16>(L.x0));
+    hipLaunchKernelGGL((conv_fwd<4, 32>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.x0),
+                       at<bf16>(L.w1), at<float>(L.par) + 32 * 4 * 9, at<float>(L.z1), at<bf16>(L.a1), nx, ny, 1);
+    hipLaunchKernelGGL((conv_fwd<32, 32>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.a1),
+                       at<bf16>(L.w2), at<float>(L.par) + (32 * 4 * 9 + 32) + 32 * 32 * 9, at<float>(L.z2),
+                       at<bf16>(L.a2), nx, ny, 1);
+    // layer 3: no activation; its bf16 copy goes to the (unused) g3 slot first
+    hipLaunchKernelGGL((conv_fwd<32, 4>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.a2),
+                       at<bf16>(L.w3), at<float>(L.par) + (NPARAM - 4), at<float>(L.z3), at<bf16>(L.g3), nx, ny, 0);
+    return hip(hipGetLastError(), "closure forward");
+  }
+
+  olb_status backward(const double* dev_m, const double* dev_ref) {
+    using namespace olbk;
+    float* grad = at<float>(L.grad);
+    olb_status s = hip(hipMemsetAsync(grad, 0, NPARAM * 4, stream), "grad clear");
+    if (s) return s;
+    s = hip(hipMemsetAsync(at<float>(L.loss), 0, 4, stream), "loss clear");
+    if (s) return s;
+    hipLaunchKernelGGL(loss_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, at<float>(L.z3), dev_m, dev_ref,
+                       P, norm, at<bf16>(L.g3), at<float>(L.loss));
+    const int O2 = 32 * 4 * 9 + 32, O3 = O2 + 32 * 32 * 9 + 32;
+    const int chunk = 1024;
+    const int wb = (P + chunk - 1) / chunk;
+    // layer 3
+    hipLaunchKernelGGL((conv_bwd_weight<32, 4>), dim3(wb), dim3(256), 0, stream, at<bf16>(L.g3), at<bf16>(L.a2),
+                       grad + O3, nx, ny, chunk);
+    hipLaunchKernelGGL((bias_grad<4>), dim3(256), dim3(256), 0, stream, at<bf16>(L.g3), grad + O3 + 4 * 32 * 9, P);
+    hipLaunchKernelGGL((conv_bwd_data<32, 4>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.g3),
+                       at<bf16>(L.w3), at<float>(L.z2), at<bf16>(L.g2), nx, ny);
+    // layer 2
+    hipLaunchKernelGGL((conv_bwd_weight<32, 32>), dim3(wb), dim3(256), 0, stream, at<bf16>(L.g2),
+                       at<bf16>(L.a1), grad + O2, nx, ny, chunk);
+    hipLaunchKernelGGL((bias_grad<32>), dim3(256), dim3(256), 0, stream, at<bf16>(L.g2), grad + O2 + 32 * 32 * 9, P);
+    hipLaunchKernelGGL((conv_bwd_data<32, 32>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.g2),
+                       at<bf16>(L.w2), at<float>(L.z1), at<bf16>(L.g1), nx, ny);
+    // layer 1 (the input needs no gradient)
+    hipLaunchKernelGGL((conv_bwd_weight<4, 32>), dim3(wb), dim3(256), 0, stream, at<bf16>(L.g1), at<bf16>(L.x0),
+                       grad, nx, ny, chunk);
+    hipLaunchKernelGGL((bias_grad<32>), dim3(256), dim3(256), 0, stream, at<bf16>(L.g1), grad + 32 * 4 * 9, P);
+    return hip(hipGetLastError(), "closure backward");
+  }
+
+  olb_status pack() {
+    using namespace olbk;
+    const int n = 32 * kp_of(4) + 32 * kp_of(32) + 16 * kp_of(32);
+    hipLaunchKernelGGL(pack_weights, dim3((n + 255) / 256), dim3(256), 0, stream, at<float>(L.par),
+                       at<bf16>(L.w1), at<bf16>(L.w2), at<bf16>(L.w3));
+    return hip(hipGetLastError(), "weight pack");
+  }
+};
+
+namespace {
+bool valid_size(int32_t nx, int32_t ny) { return nx >= 1 && ny >= 1 && (int64_t)nx * ny < (1 << 30); }
+}  // namespace
+
+extern "C" {
+
+olb_status olb_closure_workspace_bytes(int32_t nx, int32_t ny, size_t* bytes) {
+  if (!bytes || !valid_size(nx, ny)) return OLB_E_ARG;
+  *bytes = clayout(nx, ny).total;
+  return OLB_OK;
+}
+
+olb_status olb_closure_init(int32_t nx, int32_t ny, void* dev_workspace, size_t bytes, void* hip_stream,
+                            olb_closure** out) {
+  if (!out || !valid_size(nx, ny)) return OLB_E_ARG;
+  *out = nullptr;
+  const CLayout L = clayout(nx, ny);
+  if (!dev_workspace || bytes < L.total || ((uintptr_t)dev_workspace % AL) != 0) return OLB_E_WORKSPACE;
+  olb_closure* c = new (std::nothrow) olb_closure();
+  if (!c) return OLB_E_WORKSPACE;
+  c->nx = nx;
+  c->ny = ny;
+  c->P = nx * ny;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (unsigned char*)dev_workspace;
+  c->L = L;
+  for (int k = 0; k < 4; ++k) {
+    c->norm.in_mean[k] = 0.f;
+    c->norm.in_inv_scale[k] = 1.f;
+    c->norm.out_scale[k] = 1.f;
+  }
+  olb_status s = c->hip(hipMemsetAsync(c->ws, 0, L.total, c->stream), "workspace clear");
+  if (!s) s = c->hip(hipStreamSynchronize(c->stream), "stream sync");
+  if (s) {
+    delete c;
+    return s;
+  }
+  *out = c;
+  return OLB_OK;
+}
+
+olb_status olb_closure_set_norm(olb_closure* c, const double in_mean[4], const double in_scale[4],
+                                const double out_scale[4]) {
+  if (!c || !in_mean || !in_scale || !out_scale) return OLB_E_ARG;
+  for (int k = 0; k < 4; ++k) {
+    if (!(in_scale[k] > 0.0) || !(out_scale[k] > 0.0) || !std::isfinite(in_mean[k])) return OLB_E_ARG;
+    c->norm.in_mean[k] = (float)in_mean[k];
+    c->norm.in_inv_scale[k] = (float)(1.0 / in_scale[k]);
+    c->norm.out_scale[k] = (float)out_scale[k];
+  }
+  return OLB_OK;
+}
+
+olb_status olb_closure_set_params(olb_closure* c, const float* params) {
+  if (!c || !params) return OLB_E_ARG;
+  for (int k = 0; k < NPARAM; ++k)
+    if (!std::isfinite(params[k])) return OLB_E_ARG;
+  olb_status s = c->hip(hipMemcpyAsync(c->at<float>(c->L.par), params, NPARAM * 4, hipMemcpyHostToDevice,
+                                       c->stream), "param upload");
+  if (s) return s;
+  s = c->hip(hipMemsetAsync(c->at<float>(c->L.am), 0, NPARAM * 4, c->stream), "adam clear");
+  if (!s) s = c->hip(hipMemsetAsync(c->at<float>(c->L.av), 0, NPARAM * 4, c->stream), "adam clear");
+  if (!s) s = c->pack();
+  if (!s) s = c->hip(hipStreamSynchronize(c->stream), "stream sync");
+  if (s) return s;
+  c->adam_t = 0;
+  c->have_params = true;
+  return OLB_OK;
+}
+
+olb_status olb_closure_get_params(olb_closure* c, float* params) {
+  if (!c || !params) return OLB_E_ARG;
+  olb_status s = c->hip(hipMemcpyAsync(params, c->at<float>(c->L.par), NPARAM * 4, hipMemcpyDeviceToHost,
+                                       c->stream), "param download");
+  if (s) return s;
+  return c->hip(hipStreamSynchronize(c->stream), "stream sync");
+}
+
+olb_status olb_closure_forward(olb_closure* c, const double* dev_moments, double* dev_delta) {
+  if (!c || !dev_moments || !dev_delta) return OLB_E_ARG;
+  if (!c->have_params) return OLB_E_STATE;
+  olb_status s = c->forward(dev_moments);
+  if (s) return s;
+  hipLaunchKernelGGL(olbk::delta_kernel, dim3((c->P + 255) / 256), dim3(256), 0, c->stream,
+                     c->at<float>(c->L.z3), c->P, c->norm, dev_delta);
+  return c->hip(hipGetLastError(), "delta kernel");
+}
+
+olb_status olb_closure_gradients(olb_closure* c, const double* dev_moments, const double* dev_reference,
+                                 float* grad, float* loss) {
+  if (!c || !dev_moments || !dev_reference || !grad) return OLB_E_ARG;
+  if (!c->have_params) return OLB_E_STATE;
+  olb_status s = c->forward(dev_moments);
+  if (!s) s = c->backward(dev_moments, dev_reference);
+  if (!s) s = c->hip(hipMemcpyAsync(grad, c->at<float>(c->L.grad), NPARAM * 4, hipMemcpyDeviceToHost,
+                                    c->stream), "grad download");
+  if (!s && loss)
+    s = c->hip(hipMemcpyAsync(loss, c->at<float>(c->L.loss), 4, hipMemcpyDeviceToHost, c->stream), "loss");
+  if (!s) s = c->hip(hipStreamSynchronize(c->stream), "stream sync");
+  return s;
+}
+
+olb_status olb_closure_train_step(olb_closure* c, const double* dev_moments, const double* dev_reference,
+                                  float lr, float* loss) {
+  if (!c || !dev_moments || !dev_reference || !(lr > 0.f)) return OLB_E_ARG;
+  if (!c->have_params) return OLB_E_STATE;
+  olb_status s = c->forward(dev_moments);
+  if (!s) s = c->backward(dev_moments, dev_reference);
+  if (s) return s;
+  c->adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.0f / (1.0f - std::pow(b1, (float)c->adam_t));
+  const float c2 = 1.0f / (1.0f - std::pow(b2, (float)c->adam_t));
+  hipLaunchKernelGGL(olbk::adam_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, c->stream,
+                     c->at<float>(c->L.par), c->at<float>(c->L.grad), c->at<float>(c->L.am),
+                     c->at<float>(c->L.av), NPARAM, lr, b1, b2, eps, c1, c2);
+  s = c->hip(hipGetLastError(), "adam kernel");
+  if (!s) s = c->pack();
+  if (!s && loss) {
+    s = c->hip(hipMemcpyAsync(loss, c->at<float>(c->L.loss), 4, hipMemcpyDeviceToHost, c->stream), "loss");
+    if (!s) s = c->hip(hipStreamSynchronize(c->stream), "stream sync");
+  }
+  return s;
+}
+
+olb_status olb_closure_apply(olb_closure* c, olb_ctx* coarse, int32_t* skipped) {
+  if (!c || !coarse) return OLB_E_ARG;
+  if (!c->have_params) return OLB_E_STATE;
+  olbk::InstanceView v;
+  olb_status s = olbk::instance_view(coarse, &v);
+  if (s) return s;
+  if (v.g.nx != c->nx || v.g.ny != c->ny) return OLB_E_ARG;
+  if (v.stream != c->stream) {
+    // order the two streams: the closure waits for the solver's queued steps
+    s = c->hip(hipStreamSynchronize(v.stream), "solver sync");
+    if (s) return s;
+  }
+  s = olb_moments_device(coarse, c->at<double>(c->L.mom));
+  if (s) return s;
+  if (v.stream != c->stream) {
+    s = c->hip(hipStreamSynchronize(v.stream), "solver sync");
+    if (s) return s;
+  }
+  s = olb_closure_forward(c, c->at<double>(c->L.mom), c->at<double>(c->L.delta));
+  if (s) return s;
+  s = c->hip(hipMemsetAsync(c->at<int>(c->L.skip), 0, 4, c->stream), "skip clear");
+  if (s) return s;
+  dim3 grid((c->nx + 63) / 64, c->ny);
+  if (v.real_bytes == 8)
+    hipLaunchKernelGGL(olbk::apply_kernel<double>, grid, dim3(64), 0, c->stream, c->at<double>(c->L.mom),
+                       c->at<double>(c->L.delta), v.g, (double*)v.f, v.b, c->at<int>(c->L.skip));
+  else
+    hipLaunchKernelGGL(olbk::apply_kernel<float>, grid, dim3(64), 0, c->stream, c->at<double>(c->L.mom),
+                       c->at<double>(c->L.delta), v.g, (float*)v.f, v.b, c->at<int>(c->L.skip));
+  s = c->hip(hipGetLastError(), "apply kernel");
+  if (s) return s;
+  // the carried (n, Delta p) of the solver must follow the corrected f
+  s = olbk::refresh_carry(coarse, c->stream);
+  if (s) return s;
+  if (skipped) {
+    s = c->hip(hipMemcpyAsync(skipped, c->at<int>(c->L.skip), 4, hipMemcpyDeviceToHost, c->stream), "skip");
+    if (s) return s;
+  }
+  // the solver's next steps on its own stream must see the corrected f
+  if (skipped || v.stream != c->stream) s = c->hip(hipStreamSynchronize(c->stream), "stream sync");
+  return s;
+}
+
+olb_status olb_restrict(const double* dev_fine, int32_t fnx, int32_t fny, int32_t factor, double* dev_coarse,
+                        void* hip_stream) {
+  if (!dev_fine || !dev_coarse || factor < 1 || fnx < factor || fny < factor || fnx % factor ||
+      fny % factor)
+    return OLB_E_ARG;
+  const int cnx = fnx / factor, cny = fny / factor;
+  hipLaunchKernelGGL(olbk::restrict_kernel, dim3((cnx + 63) / 64, cny), dim3(64), 0, (hipStream_t)hip_stream,
+                     dev_fine, fnx, fny, factor, dev_coarse);
+  return hipGetLastError() == hipSuccess ? OLB_OK : OLB_E_DEVICE;
+}
+
+const char* olb_closure_last_error(const olb_closure* c) { return c ? c->err.c_str() : "null closure"; }
+void olb_closure_free(olb_closure* c) { delete c; }
+
+}  // extern "C"

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/olb.h"
+
 namespace olbk {
 
 // Storage of one distribution array: 25 planes, each (ny + 6) rows of nx
@@ -69,6 +71,8 @@ hipError_t launch_walls(const WallBatchArgs& a, int real_bytes, int wall_blocks,
 // f = f^eq(n, u, T) from device fields [4][ny][nx]; also writes the carry.
 hipError_t launch_init(const Geometry& g, const double* fields, void* f, double* carry,
                        double rho0, double a, double b, int real_bytes, hipStream_t s);
+// *bad = 1 if a node of device fields [4][ny][nx] is outside the domain.
+hipError_t launch_check_fields(const Geometry& g, const double* fields, double b, int* bad, hipStream_t s);
 // n, u_x, u_y, T planes [4][ny][nx] of f.
 hipError_t launch_moments(const Geometry& g, const void* f, double* out, double rho0,
                           int real_bytes, hipStream_t s);
@@ -80,5 +84,18 @@ hipError_t launch_pack(const Geometry& g, const void* f, double* out, double rho
                        int real_bytes, hipStream_t s);
 hipError_t launch_unpack(const Geometry& g, const double* in, void* f, double rho0,
                          int real_bytes, hipStream_t s);
+
+// The stored f^n of a single-instance context, for kernels outside the stage
+// update (the learned closure) that modify it in place.
+struct InstanceView {
+  Geometry g;
+  void* f;           // stored f^n (25 planes)
+  int real_bytes;    // 8: double, 4: float departure from w_k rho0
+  double rho0, b;
+  hipStream_t stream;
+};
+olb_status instance_view(olb_ctx* c, InstanceView* v);
+// Recompute the carried (n, Delta p) of f^n after f^n changed, on stream s.
+olb_status refresh_carry(olb_ctx* c, hipStream_t s);
 
 }  // namespace olbk

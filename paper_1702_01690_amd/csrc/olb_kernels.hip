@@ -19,6 +19,7 @@
 
 #include "olb_consts.hpp"
 #include "olb_device.hpp"
+#include "olb_feq.hpp"
 
 namespace olbk {
 using namespace olbc;
@@ -120,21 +121,6 @@ __device__ __forceinline__ void sums25(const Real* f, double rho0, double& n, do
   if (std::is_same<Real, float>::value) {
     n += rho0;
     e += 2.0 * rho0;
-  }
-}
-
-// Hermite equilibrium factor g_k(u, T) = W_k (1 + h_k(u, T)) (Eq. g_alpha,
-// N = 4, m = 1): h = u He1 + (th + u^2)/2 He2 + (u^3 + 3 u th)/6 He3
-//                 + (u^4 + 6 u^2 th + 3 th^2)/24 He4,  th = T - 1.
-__device__ __forceinline__ void hfac(double u, double th, double h[5]) {
-  const double u2 = u * u;
-  const double c1 = u;
-  const double c2 = 0.5 * (th + u2);
-  const double c3 = (1.0 / 6.0) * u * (u2 + 3.0 * th);
-  const double c4 = (1.0 / 24.0) * (u2 * u2 + 6.0 * u2 * th + 3.0 * th * th);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    h[k] = c1 * HE.v[1][k] + c2 * HE.v[2][k] + c3 * HE.v[3][k] + c4 * HE.v[4][k];
   }
 }
 
@@ -724,6 +710,23 @@ hipError_t launch_walls(const WallBatchArgs& a, int real_bytes, int wall_blocks,
 }
 
 static dim3 cell_grid(const Geometry& g) { return dim3((g.nx + 63) / 64, g.ny); }
+
+// bad = 1 if any node of device fields [4][ny][nx] is outside the model's
+// domain (non-finite, n outside (0, 1/b), T <= 0)
+__global__ void check_fields_kernel(Geometry g, const double* __restrict__ fld, double b, int* __restrict__ bad) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= g.nx) return;
+  const size_t N = (size_t)g.nx * g.ny, m = (size_t)y * g.nx + x;
+  const double n = fld[m], ux = fld[N + m], uy = fld[2 * N + m], T = fld[3 * N + m];
+  const bool ok = isfinite(n) && isfinite(ux) && isfinite(uy) && isfinite(T) && n > 0.0 &&
+                  (b <= 0.0 || n * b < 1.0) && T > 0.0;
+  if (!ok) *bad = 1;
+}
+
+hipError_t launch_check_fields(const Geometry& g, const double* fields, double b, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(check_fields_kernel, cell_grid(g), dim3(64), 0, s, g, fields, b, bad);
+  return hipGetLastError();
+}
 
 hipError_t launch_init(const Geometry& g, const double* fields, void* f, double* carry,
                        double rho0, double va, double vb, int real_bytes, hipStream_t s) {

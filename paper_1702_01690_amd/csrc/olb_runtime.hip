@@ -247,6 +247,34 @@ struct Engine {
     return hip(hipStreamSynchronize(stream), "stream sync");
   }
 
+  // the same from device fields [4][ny][nx], checked on the device first
+  olb_status set_fields_device(int i, const double* fields) {
+    olb_status s = check_index(i);
+    if (s) return s;
+    if (!fields) return fail(OLB_E_ARG, "null fields");
+    const olbk::InstDesc& d = desc[i];
+    int* bad = flag + 1;
+    int h = 0;
+    s = hip(hipMemsetAsync(bad, 0, sizeof(int), stream), "flag clear");
+    if (s) return s;
+    s = hip(olbk::launch_check_fields(d.g, fields, d.b, bad, stream), "field check");
+    if (s) return s;
+    s = hip(hipMemcpyAsync(&h, bad, sizeof h, hipMemcpyDeviceToHost, stream), "flag copy");
+    if (s) return s;
+    s = hip(hipStreamSynchronize(stream), "stream sync");
+    if (s) return s;
+    if (h) return fail(OLB_E_DOMAIN, "field outside the domain (n in (0, 1/b), T > 0, finite)");
+    const size_t N = (size_t)p[i].nx * p[i].ny;
+    s = hip(hipMemcpyAsync(d.f[1], fields, 4 * N * sizeof(double), hipMemcpyDeviceToDevice, stream),
+            "field copy");
+    if (s) return s;
+    s = init_from_staging(i);
+    if (s) return s;
+    s = hip(hipMemsetAsync(flag, 0, sizeof(int), stream), "flag clear");
+    if (s) return s;
+    return hip(hipStreamSynchronize(stream), "stream sync");
+  }
+
   olb_status set_f(int i, const double* f) {
     olb_status s = check_index(i);
     if (s) return s;
@@ -531,6 +559,28 @@ struct olb_batch {
   Engine e;
 };
 
+namespace olbk {
+olb_status instance_view(olb_ctx* c, InstanceView* v) {
+  if (!c || !v) return OLB_E_ARG;
+  Engine& e = c->e;
+  if (!e.have_f[0]) return e.fail(OLB_E_STATE, "no distribution set");
+  v->g = e.desc[0].g;
+  v->f = e.desc[0].f[0];
+  v->real_bytes = e.rb;
+  v->rho0 = e.desc[0].rho0;
+  v->b = e.desc[0].b;
+  v->stream = e.stream;
+  return OLB_OK;
+}
+
+olb_status refresh_carry(olb_ctx* c, hipStream_t s) {
+  if (!c) return OLB_E_ARG;
+  Engine& e = c->e;
+  const InstDesc& d = e.desc[0];
+  return e.hip(launch_carry(d.g, d.f[0], d.carry[e.cur], d.rho0, d.a, d.b, e.rb, s), "carry kernel");
+}
+}  // namespace olbk
+
 static size_t engine_bytes(const olb_params* p, int32_t n) {
   size_t total = head_bytes(n);
   for (int32_t i = 0; i < n; ++i) total += inst_layout(p[i]).total;
@@ -578,6 +628,9 @@ olb_status olb_init(const olb_params* p, void* dev_workspace, size_t bytes, void
 olb_status olb_set_fields(olb_ctx* c, const double* n, const double* ux, const double* uy,
                           const double* T) {
   return c ? c->e.set_fields(0, n, ux, uy, T) : OLB_E_ARG;
+}
+olb_status olb_set_fields_device(olb_ctx* c, const double* dev_fields) {
+  return c ? c->e.set_fields_device(0, dev_fields) : OLB_E_ARG;
 }
 olb_status olb_step(olb_ctx* c, int32_t nsteps) { return c ? c->e.step(nsteps) : OLB_E_ARG; }
 olb_status olb_sync(olb_ctx* c) { return c ? c->e.read_flag() : OLB_E_ARG; }
@@ -636,6 +689,9 @@ olb_status olb_batch_set_fields(olb_batch* b, int32_t i, const double* n, const 
                                 const double* uy, const double* T) {
   return b ? b->e.set_fields(i, n, ux, uy, T) : OLB_E_ARG;
 }
+olb_status olb_batch_set_fields_device(olb_batch* b, int32_t i, const double* dev_fields) {
+  return b ? b->e.set_fields_device(i, dev_fields) : OLB_E_ARG;
+}
 olb_status olb_batch_set_f(olb_batch* b, int32_t i, const double* f) {
   return b ? b->e.set_f(i, f) : OLB_E_ARG;
 }
@@ -644,6 +700,9 @@ olb_status olb_batch_step(olb_batch* b, int32_t nsteps) { return b ? b->e.step(n
 olb_status olb_batch_sync(olb_batch* b) { return b ? b->e.read_flag() : OLB_E_ARG; }
 olb_status olb_batch_moments(olb_batch* b, int32_t i, double* n, double* ux, double* uy, double* T) {
   return b ? b->e.moments(i, n, ux, uy, T) : OLB_E_ARG;
+}
+olb_status olb_batch_moments_device(olb_batch* b, int32_t i, double* dev_out) {
+  return b ? b->e.moments_device(i, dev_out) : OLB_E_ARG;
 }
 olb_status olb_batch_wall_density(olb_batch* b, int32_t i, double* lo, double* hi) {
   return b ? b->e.wall_density(i, lo, hi) : OLB_E_ARG;

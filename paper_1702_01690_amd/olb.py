@@ -47,6 +47,7 @@ def make_params(d):
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
 _vp = ctypes.c_void_p
 _LIB = None
 
@@ -82,6 +83,21 @@ _SIGS = {
     "olb_batch_tiles": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "olb_batch_last_error": ([_vp], ctypes.c_char_p),
     "olb_batch_free": ([_vp], None),
+    "olb_set_fields_device": ([_vp, _vp], ctypes.c_int),
+    "olb_batch_set_fields_device": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
+    "olb_batch_moments_device": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
+    "olb_closure_workspace_bytes": ([ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "olb_closure_init": ([ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "olb_closure_set_norm": ([_vp, _dp, _dp, _dp], ctypes.c_int),
+    "olb_closure_set_params": ([_vp, _fp], ctypes.c_int),
+    "olb_closure_get_params": ([_vp, _fp], ctypes.c_int),
+    "olb_closure_forward": ([_vp, _vp, _vp], ctypes.c_int),
+    "olb_closure_gradients": ([_vp, _vp, _vp, _fp, _fp], ctypes.c_int),
+    "olb_closure_train_step": ([_vp, _vp, _vp, ctypes.c_float, _fp], ctypes.c_int),
+    "olb_closure_apply": ([_vp, _vp, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "olb_closure_last_error": ([_vp], ctypes.c_char_p),
+    "olb_closure_free": ([_vp], None),
+    "olb_restrict": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp], ctypes.c_int),
 }
 
 
@@ -108,7 +124,9 @@ def _ptr(a):
 def _check(rc, h=None, batch=False):
     if rc != OLB_OK:
         if h:
-            msg = (lib().olb_batch_last_error(h) if batch else lib().olb_last_error(h)).decode()
+            get = {False: lib().olb_last_error, True: lib().olb_batch_last_error,
+                   "closure": lib().olb_closure_last_error}[batch]
+            msg = get(h).decode()
         else:
             msg = ""
         raise OlbError(rc, msg or lib().olb_strerror(rc).decode())
@@ -133,6 +151,10 @@ def olb_init(params, workspace_ptr, nbytes, stream_ptr):
 def olb_set_fields(h, n, ux, uy, T):
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (n, ux, uy, T)]
     _check(lib().olb_set_fields(h, *(_ptr(a) for a in arrs)), h)
+
+
+def olb_set_fields_device(h, dev_ptr):
+    _check(lib().olb_set_fields_device(h, _vp(dev_ptr)), h)
 
 
 def olb_step(h, nsteps):
@@ -186,6 +208,12 @@ def olb_free(h):
 
 # ------------------------------------------------------------- convenience --
 
+def _need_device_f64(t, count):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == count):
+        raise ValueError(f"expected a contiguous float64 CUDA tensor of {count} values, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
 class Lattice:
     """One context on ``device`` with a torch-owned workspace and stream."""
 
@@ -233,7 +261,14 @@ class Lattice:
         return olb_moments(self.h, self.shape)
 
     def moments_device(self, out):
+        """Moments into a contiguous float64 CUDA tensor of 4 * ny * nx values."""
+        _need_device_f64(out, 4 * self.nx * self.ny)
         olb_moments_device(self.h, out.data_ptr())
+
+    def set_fields_device(self, fields):
+        """f <- f^eq of a contiguous float64 CUDA tensor [4][ny][nx]."""
+        _need_device_f64(fields, 4 * self.nx * self.ny)
+        olb_set_fields_device(self.h, fields.data_ptr())
 
     def get_f(self):
         return olb_get_f(self.h, self.shape)
@@ -278,6 +313,14 @@ def olb_batch_init(params_list, workspace_ptr, nbytes, stream_ptr):
 def olb_batch_set_fields(h, i, n, ux, uy, T):
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (n, ux, uy, T)]
     _check(lib().olb_batch_set_fields(h, int(i), *(_ptr(a) for a in arrs)), h, True)
+
+
+def olb_batch_set_fields_device(h, i, dev_ptr):
+    _check(lib().olb_batch_set_fields_device(h, int(i), _vp(dev_ptr)), h, True)
+
+
+def olb_batch_moments_device(h, i, dev_ptr):
+    _check(lib().olb_batch_moments_device(h, int(i), _vp(dev_ptr)), h, True)
 
 
 def olb_batch_set_f(h, i, f):
@@ -392,6 +435,16 @@ class Batch:
     def moments(self, i):
         return olb_batch_moments(self.h, i, self.shape(i))
 
+    def moments_device(self, i, out):
+        ny, nx = self.shape(i)
+        _need_device_f64(out, 4 * nx * ny)
+        olb_batch_moments_device(self.h, i, out.data_ptr())
+
+    def set_fields_device(self, i, fields):
+        ny, nx = self.shape(i)
+        _need_device_f64(fields, 4 * nx * ny)
+        olb_batch_set_fields_device(self.h, i, fields.data_ptr())
+
     def wall_density(self, i):
         return olb_batch_wall_density(self.h, i, self.shape(i)[1])
 
@@ -406,3 +459,151 @@ class Batch:
 
     def tiles(self):
         return olb_batch_tiles(self.h)
+
+
+# ------------------------------------------------------------------ closure --
+
+NPARAM = 11588
+# offsets of the blocks of the flat parameter vector
+PARAM_BLOCKS = (("W1", (32, 4, 3, 3)), ("b1", (32,)), ("W2", (32, 32, 3, 3)), ("b2", (32,)),
+                ("W3", (4, 32, 3, 3)), ("b3", (4,)))
+
+
+def olb_closure_workspace_bytes(nx, ny):
+    n = ctypes.c_size_t()
+    _check(lib().olb_closure_workspace_bytes(int(nx), int(ny), ctypes.byref(n)))
+    return int(n.value)
+
+
+def olb_closure_init(nx, ny, workspace_ptr, nbytes, stream_ptr):
+    h = _vp()
+    _check(lib().olb_closure_init(int(nx), int(ny), _vp(workspace_ptr), nbytes, _vp(stream_ptr),
+                                  ctypes.byref(h)))
+    return h
+
+
+def _f32(a, count):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.size != count:
+        raise ValueError(f"expected {count} values, got {a.size}")
+    return a
+
+
+def olb_closure_set_norm(h, in_mean, in_scale, out_scale):
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (in_mean, in_scale, out_scale)]
+    for a in arrs:
+        if a.size != 4:
+            raise ValueError("normalisation vectors have 4 entries")
+    _check(lib().olb_closure_set_norm(h, *(_ptr(a) for a in arrs)), h, "closure")
+
+
+def olb_closure_set_params(h, params):
+    p = _f32(params, NPARAM)
+    _check(lib().olb_closure_set_params(h, p.ctypes.data_as(_fp)), h, "closure")
+
+
+def olb_closure_get_params(h):
+    p = np.empty(NPARAM, dtype=np.float32)
+    _check(lib().olb_closure_get_params(h, p.ctypes.data_as(_fp)), h, "closure")
+    return p
+
+
+def olb_closure_forward(h, dev_moments, dev_delta):
+    _check(lib().olb_closure_forward(h, _vp(dev_moments), _vp(dev_delta)), h, "closure")
+
+
+def olb_closure_gradients(h, dev_moments, dev_reference):
+    g = np.empty(NPARAM, dtype=np.float32)
+    loss = np.zeros(1, dtype=np.float32)
+    _check(lib().olb_closure_gradients(h, _vp(dev_moments), _vp(dev_reference), g.ctypes.data_as(_fp),
+                                       loss.ctypes.data_as(_fp)), h, "closure")
+    return g, float(loss[0])
+
+
+def olb_closure_train_step(h, dev_moments, dev_reference, lr, want_loss=True):
+    loss = np.zeros(1, dtype=np.float32)
+    ptr = loss.ctypes.data_as(_fp) if want_loss else None
+    _check(lib().olb_closure_train_step(h, _vp(dev_moments), _vp(dev_reference), ctypes.c_float(lr), ptr),
+           h, "closure")
+    return float(loss[0]) if want_loss else None
+
+
+def olb_closure_apply(h, ctx):
+    skipped = ctypes.c_int32()
+    _check(lib().olb_closure_apply(h, ctx, ctypes.byref(skipped)), h, "closure")
+    return skipped.value
+
+
+def olb_closure_free(h):
+    lib().olb_closure_free(h)
+
+
+def olb_restrict(dev_fine, fnx, fny, factor, dev_coarse, stream_ptr):
+    _check(lib().olb_restrict(_vp(dev_fine), int(fnx), int(fny), int(factor), _vp(dev_coarse),
+                              _vp(stream_ptr)))
+
+
+def restrict(fine, fnx, fny, factor, out=None, stream=None):
+    """Conservative restriction of a float64 CUDA tensor [4][fny][fnx]."""
+    import torch
+    _need_device_f64(fine, 4 * fnx * fny)
+    cnx, cny = fnx // factor, fny // factor
+    if out is None:
+        out = torch.empty(4 * cnx * cny, dtype=torch.float64, device=fine.device)
+    _need_device_f64(out, 4 * cnx * cny)
+    stream = stream if stream is not None else torch.cuda.current_stream(fine.device)
+    olb_restrict(fine.data_ptr(), fnx, fny, factor, out.data_ptr(), stream.cuda_stream)
+    return out
+
+
+class Closure:
+    """The learned coarse-lattice closure on ``device`` (workspace and stream
+    from torch)."""
+
+    def __init__(self, nx, ny, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the closure kernels have no CPU path")
+        self.nx, self.ny = int(nx), int(ny)
+        self.device = torch.device(device)
+        nbytes = olb_closure_workspace_bytes(self.nx, self.ny)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = olb_closure_init(self.nx, self.ny, aligned, nbytes, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            olb_closure_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _planes(self, t):
+        _need_device_f64(t, 4 * self.nx * self.ny)
+        return t.data_ptr()
+
+    def set_norm(self, in_mean, in_scale, out_scale):
+        olb_closure_set_norm(self.h, in_mean, in_scale, out_scale)
+
+    def set_params(self, params):
+        olb_closure_set_params(self.h, params)
+
+    def get_params(self):
+        return olb_closure_get_params(self.h)
+
+    def forward(self, moments, delta):
+        olb_closure_forward(self.h, self._planes(moments), self._planes(delta))
+
+    def gradients(self, moments, reference):
+        return olb_closure_gradients(self.h, self._planes(moments), self._planes(reference))
+
+    def train_step(self, moments, reference, lr, want_loss=True):
+        return olb_closure_train_step(self.h, self._planes(moments), self._planes(reference), lr, want_loss)
+
+    def apply(self, lattice):
+        return olb_closure_apply(self.h, lattice.h)

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
     # and the binding wraps each one under the same name
     for n in names:
-        if n in ("olb_last_error", "olb_strerror", "olb_batch_last_error"):
+        if n in ("olb_last_error", "olb_strerror", "olb_batch_last_error", "olb_closure_last_error"):
             continue
         assert hasattr(olb, n), n
 
@@ -70,3 +70,28 @@ def test_init_rejects_small_or_misaligned_workspace_without_touching_device():
     rc = L.olb_init(ctypes.byref(p), ctypes.c_void_p(4096 + 8), nb, None, ctypes.byref(h))
     assert rc == olb.OLB_E_WORKSPACE
     assert L.olb_strerror(olb.OLB_E_CFL).decode().startswith("CFL")
+
+
+def test_closure_validation_without_device_work():
+    olb, L = _lib()
+    nb = olb.olb_closure_workspace_bytes(64, 48)
+    # activations (bf16 and FP32 pre-activations), moments, parameters and Adam state
+    assert nb >= 64 * 48 * (32 * 2 * 2 + 32 * 4 * 2) + 4 * olb.NPARAM * 4
+    for nx, ny in ((0, 4), (4, -1)):
+        with pytest.raises(olb.OlbError) as e:
+            olb.olb_closure_workspace_bytes(nx, ny)
+        assert e.value.code == olb.OLB_E_ARG
+    with pytest.raises(olb.OlbError) as e:
+        olb.olb_closure_init(8, 8, 0, 1 << 20, 0)
+    assert e.value.code == olb.OLB_E_WORKSPACE
+    with pytest.raises(olb.OlbError) as e:
+        olb.olb_closure_init(8, 8, 256 * 1000 + 8, 1 << 20, 0)      # misaligned
+    assert e.value.code == olb.OLB_E_WORKSPACE
+    with pytest.raises(olb.OlbError) as e:
+        olb.olb_closure_init(8, 8, 256 * 1000, 16, 0)               # too small
+    assert e.value.code == olb.OLB_E_WORKSPACE
+    for fnx, fny, r in ((10, 8, 4), (8, 8, 0), (2, 8, 4)):
+        with pytest.raises(olb.OlbError) as e:
+            olb.olb_restrict(1 << 20, fnx, fny, r, 1 << 21, 0)
+        assert e.value.code == olb.OLB_E_ARG
+    assert L.olb_closure_last_error(None) == b"null closure"

@@ -220,8 +220,17 @@ olb_status olb_closure_set_norm(olb_closure* c, const double in_mean[4], const d
 olb_status olb_closure_set_params(olb_closure* c, const float* params);
 olb_status olb_closure_get_params(olb_closure* c, float* params);
 /* Network output for device moments [4][ny][nx] -> device corrections
- * [4][ny][nx] (double).  Asynchronous.  OLB_E_STATE before set_params. */
+ * [4][ny][nx] (double), scaled by out_scale and projected as set by
+ * olb_closure_set_conserve.  Asynchronous.  OLB_E_STATE before set_params. */
 olb_status olb_closure_forward(olb_closure* c, const double* dev_moments, double* dev_delta);
+/* Conservative projection of forward / apply: bit c of mask (c = 0 n,
+ * 1 u_x, 2 u_y, 3 T) removes the lattice mean of that correction channel, so
+ * that, e.g., the total mass is unchanged by apply (bit 0).  Default 7 (n,
+ * u_x, u_y: the fine and coarse runs conserve mass and, to rounding and
+ * stencil order, momentum; T keeps its mean because the fine run heats up
+ * as its unresolved fluctuations decay).  The loss and gradients see the raw
+ * network output.  OLB_E_ARG outside 0..15. */
+olb_status olb_closure_set_conserve(olb_closure* c, int32_t mask);
 /* Training pair: dev_moments (the coarse run's moments, the network input)
  * and dev_reference (the restricted fine moments at the same time), both
  * device [4][ny][nx].  Loss L = mean over nodes and the 4 channels of
@@ -241,6 +250,14 @@ olb_status olb_closure_train_step(olb_closure* c, const double* dev_moments, con
  * lattice's carried state is refreshed.  Synchronises both streams when the
  * lattice runs on another stream. */
 olb_status olb_closure_apply(olb_closure* c, olb_ctx* coarse, int32_t* skipped);
+/* Move the moments of a coarse lattice to dev_target [4][ny][nx] keeping its
+ * non-equilibrium part: f <- f + f^eq(target) - f^eq(m) at nodes where the
+ * target is admissible (others counted in *skipped).  The moments m before
+ * the change go to dev_moments (device [4][ny][nx], may be NULL).  Used to
+ * make training pairs along a coarse run held on the restricted fine one
+ * (a perfect closure); needs no parameters.  Synchronisation as apply. */
+olb_status olb_closure_nudge(olb_closure* c, olb_ctx* coarse, const double* dev_target, double* dev_moments,
+                             int32_t* skipped);
 const char* olb_closure_last_error(const olb_closure* c);
 void olb_closure_free(olb_closure* c);
 

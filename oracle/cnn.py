@@ -110,10 +110,16 @@ def forward(params, m, norm, bf16_mirror=False):
     return dict(W=W, x0=x0, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3)
 
 
-def correction(params, m, norm, bf16_mirror=False):
-    """Moment correction dm (4, H, W) = network output times out_scale."""
+def correction(params, m, norm, bf16_mirror=False, conserve_mask=0):
+    """Moment correction dm (4, H, W) = network output times out_scale; the
+    channels c with bit c of conserve_mask set have their lattice mean
+    removed (a conservative correction: zero net change of the total)."""
     out_scale = np.asarray(norm[2], dtype=np.float64)
-    return forward(params, m, norm, bf16_mirror)["z3"] * out_scale[:, None, None]
+    z3 = forward(params, m, norm, bf16_mirror)["z3"]
+    for c in range(4):
+        if (conserve_mask >> c) & 1:
+            z3[c] = z3[c] - z3[c].mean()
+    return z3 * out_scale[:, None, None]
 
 
 def loss_and_gradient(params, m, ref, norm, bf16_mirror=False):

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -357,24 +358,51 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
   w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
-// network output (normalised) -> correction planes (FP64)
-__global__ void delta_kernel(const float* __restrict__ Z3, int P, Norm nm, double* __restrict__ delta) {
+// channel sums of the network output (double), for the conservative projection
+__global__ void __launch_bounds__(256) output_sums(const float* __restrict__ Z3, int P, double* __restrict__ sums) {
+  __shared__ double part[4][256];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] += (double)Z3[(size_t)p * 4 + c];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) part[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) part[c][threadIdx.x] += part[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) atomicAdd(&sums[threadIdx.x], part[threadIdx.x][0]);
+}
+
+// network output (normalised) -> correction planes (FP64); channels in
+// conserve_mask lose their lattice mean (sums from output_sums)
+__global__ void delta_kernel(const float* __restrict__ Z3, int P, Norm nm, const double* __restrict__ sums,
+                             int conserve_mask, double* __restrict__ delta) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) delta[(size_t)c * P + p] = (double)Z3[(size_t)p * 4 + c] * nm.out_scale[c];
+  for (int c = 0; c < 4; ++c) {
+    const double mean = ((conserve_mask >> c) & 1) ? sums[c] / (double)P : 0.0;
+    delta[(size_t)c * P + p] = ((double)Z3[(size_t)p * 4 + c] - mean) * (double)nm.out_scale[c];
+  }
 }
 
-// f <- f + f^eq(m + dm) - f^eq(m) where the corrected moments are admissible
-// (finite, 0 < n < 1/b, T > 0); other nodes keep f (counted in skipped).
+// f <- f + f^eq(m') - f^eq(m) with m' = m + dm (absolute == 0) or m' = dm
+// (absolute == 1) where m' is admissible (finite, 0 < n < 1/b, T > 0); other
+// nodes keep f (counted in skipped).
 template <typename Real>
-__global__ void apply_kernel(const double* __restrict__ m, const double* __restrict__ dm, Geometry geo,
-                             Real* __restrict__ f, double b, int* __restrict__ skipped) {
+__global__ void apply_kernel(const double* __restrict__ m, const double* __restrict__ dm, int absolute,
+                             Geometry geo, Real* __restrict__ f, double b, int* __restrict__ skipped) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= geo.nx) return;
   const size_t N = (size_t)geo.nx * geo.ny, c = (size_t)y * geo.nx + x;
   const double n0 = m[c], ux0 = m[N + c], uy0 = m[2 * N + c], T0 = m[3 * N + c];
-  const double n1 = n0 + dm[c], ux1 = ux0 + dm[N + c], uy1 = uy0 + dm[2 * N + c], T1 = T0 + dm[3 * N + c];
+  const double base = absolute ? 0.0 : 1.0;
+  const double n1 = base * n0 + dm[c], ux1 = base * ux0 + dm[N + c], uy1 = base * uy0 + dm[2 * N + c],
+               T1 = base * T0 + dm[3 * N + c];
   const bool ok = isfinite(n1) && isfinite(ux1) && isfinite(uy1) && isfinite(T1) && n1 > 0.0 &&
                   (b <= 0.0 || n1 * b < 1.0) && T1 > 0.0;
   if (!ok) {
@@ -412,7 +440,7 @@ constexpr size_t AL = 256;
 size_t al(size_t v) { return (v + AL - 1) / AL * AL; }
 
 struct CLayout {
-  size_t x0, z1, a1, z2, a2, z3, g3, g2, g1, mom, delta, par, grad, am, av, w1, w2, w3, loss, skip, total;
+  size_t x0, z1, a1, z2, a2, z3, g3, g2, g1, mom, delta, par, grad, am, av, w1, w2, w3, loss, skip, sums, total;
 };
 
 CLayout clayout(int nx, int ny) {
@@ -440,6 +468,7 @@ CLayout clayout(int nx, int ny) {
   L.w3 = take(16 * olbk::kp_of(32) * 2);
   L.loss = take(4);
   L.skip = take(4);
+  L.sums = take(4 * 8);
   L.total = o;
   return L;
 }
@@ -452,6 +481,7 @@ struct olb_closure {
   CLayout L;
   olbk::Norm norm;
   int adam_t = 0;
+  int conserve_mask = 7;  // n, u_x, u_y corrections are made mean-free
   bool have_params = false;
   std::string err;
 
@@ -603,9 +633,23 @@ olb_status olb_closure_forward(olb_closure* c, const double* dev_moments, double
   if (!c->have_params) return OLB_E_STATE;
   olb_status s = c->forward(dev_moments);
   if (s) return s;
+  double* sums = c->at<double>(c->L.sums);
+  if (c->conserve_mask) {
+    s = c->hip(hipMemsetAsync(sums, 0, 4 * sizeof(double), c->stream), "sums clear");
+    if (s) return s;
+    const int blocks = std::min(1024, (c->P + 255) / 256);
+    hipLaunchKernelGGL(olbk::output_sums, dim3(blocks), dim3(256), 0, c->stream, c->at<float>(c->L.z3), c->P,
+                       sums);
+  }
   hipLaunchKernelGGL(olbk::delta_kernel, dim3((c->P + 255) / 256), dim3(256), 0, c->stream,
-                     c->at<float>(c->L.z3), c->P, c->norm, dev_delta);
+                     c->at<float>(c->L.z3), c->P, c->norm, sums, c->conserve_mask, dev_delta);
   return c->hip(hipGetLastError(), "delta kernel");
+}
+
+olb_status olb_closure_set_conserve(olb_closure* c, int32_t mask) {
+  if (!c || mask < 0 || mask > 15) return OLB_E_ARG;
+  c->conserve_mask = mask;
+  return OLB_OK;
 }
 
 olb_status olb_closure_gradients(olb_closure* c, const double* dev_moments, const double* dev_reference,
@@ -645,9 +689,14 @@ olb_status olb_closure_train_step(olb_closure* c, const double* dev_moments, con
   return s;
 }
 
-olb_status olb_closure_apply(olb_closure* c, olb_ctx* coarse, int32_t* skipped) {
+}  // extern "C"
+
+namespace {
+// moments of the coarse lattice into m_buf, then f <- f + f^eq(m') - f^eq(m)
+// with m' = m + network(m) (target == nullptr) or m' = target
+olb_status correct(olb_closure* c, olb_ctx* coarse, const double* target, double* m_buf, int32_t* skipped) {
   if (!c || !coarse) return OLB_E_ARG;
-  if (!c->have_params) return OLB_E_STATE;
+  if (!target && !c->have_params) return OLB_E_STATE;
   olbk::InstanceView v;
   olb_status s = olbk::instance_view(coarse, &v);
   if (s) return s;
@@ -657,23 +706,28 @@ olb_status olb_closure_apply(olb_closure* c, olb_ctx* coarse, int32_t* skipped) 
     s = c->hip(hipStreamSynchronize(v.stream), "solver sync");
     if (s) return s;
   }
-  s = olb_moments_device(coarse, c->at<double>(c->L.mom));
+  if (!m_buf) m_buf = c->at<double>(c->L.mom);
+  s = olb_moments_device(coarse, m_buf);
   if (s) return s;
   if (v.stream != c->stream) {
     s = c->hip(hipStreamSynchronize(v.stream), "solver sync");
     if (s) return s;
   }
-  s = olb_closure_forward(c, c->at<double>(c->L.mom), c->at<double>(c->L.delta));
-  if (s) return s;
+  const int absolute = target != nullptr;
+  if (!target) {
+    s = olb_closure_forward(c, m_buf, c->at<double>(c->L.delta));
+    if (s) return s;
+    target = c->at<double>(c->L.delta);
+  }
   s = c->hip(hipMemsetAsync(c->at<int>(c->L.skip), 0, 4, c->stream), "skip clear");
   if (s) return s;
   dim3 grid((c->nx + 63) / 64, c->ny);
   if (v.real_bytes == 8)
-    hipLaunchKernelGGL(olbk::apply_kernel<double>, grid, dim3(64), 0, c->stream, c->at<double>(c->L.mom),
-                       c->at<double>(c->L.delta), v.g, (double*)v.f, v.b, c->at<int>(c->L.skip));
+    hipLaunchKernelGGL(olbk::apply_kernel<double>, grid, dim3(64), 0, c->stream, m_buf, target, absolute, v.g,
+                       (double*)v.f, v.b, c->at<int>(c->L.skip));
   else
-    hipLaunchKernelGGL(olbk::apply_kernel<float>, grid, dim3(64), 0, c->stream, c->at<double>(c->L.mom),
-                       c->at<double>(c->L.delta), v.g, (float*)v.f, v.b, c->at<int>(c->L.skip));
+    hipLaunchKernelGGL(olbk::apply_kernel<float>, grid, dim3(64), 0, c->stream, m_buf, target, absolute, v.g,
+                       (float*)v.f, v.b, c->at<int>(c->L.skip));
   s = c->hip(hipGetLastError(), "apply kernel");
   if (s) return s;
   // the carried (n, Delta p) of the solver must follow the corrected f
@@ -686,6 +740,19 @@ olb_status olb_closure_apply(olb_closure* c, olb_ctx* coarse, int32_t* skipped) 
   // the solver's next steps on its own stream must see the corrected f
   if (skipped || v.stream != c->stream) s = c->hip(hipStreamSynchronize(c->stream), "stream sync");
   return s;
+}
+}  // namespace
+
+extern "C" {
+
+olb_status olb_closure_apply(olb_closure* c, olb_ctx* coarse, int32_t* skipped) {
+  return correct(c, coarse, nullptr, nullptr, skipped);
+}
+
+olb_status olb_closure_nudge(olb_closure* c, olb_ctx* coarse, const double* dev_target, double* dev_moments,
+                             int32_t* skipped) {
+  if (!dev_target) return OLB_E_ARG;
+  return correct(c, coarse, dev_target, dev_moments, skipped);
 }
 
 olb_status olb_restrict(const double* dev_fine, int32_t fnx, int32_t fny, int32_t factor, double* dev_coarse,

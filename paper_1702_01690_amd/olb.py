@@ -95,6 +95,8 @@ _SIGS = {
     "olb_closure_gradients": ([_vp, _vp, _vp, _fp, _fp], ctypes.c_int),
     "olb_closure_train_step": ([_vp, _vp, _vp, ctypes.c_float, _fp], ctypes.c_int),
     "olb_closure_apply": ([_vp, _vp, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "olb_closure_set_conserve": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "olb_closure_nudge": ([_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "olb_closure_last_error": ([_vp], ctypes.c_char_p),
     "olb_closure_free": ([_vp], None),
     "olb_restrict": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp], ctypes.c_int),
@@ -534,6 +536,17 @@ def olb_closure_apply(h, ctx):
     return skipped.value
 
 
+def olb_closure_nudge(h, ctx, dev_target, dev_moments=None):
+    skipped = ctypes.c_int32()
+    _check(lib().olb_closure_nudge(h, ctx, _vp(dev_target), _vp(dev_moments) if dev_moments else None,
+                                   ctypes.byref(skipped)), h, "closure")
+    return skipped.value
+
+
+def olb_closure_set_conserve(h, mask):
+    _check(lib().olb_closure_set_conserve(h, int(mask)), h, "closure")
+
+
 def olb_closure_free(h):
     lib().olb_closure_free(h)
 
@@ -593,6 +606,10 @@ class Closure:
     def set_params(self, params):
         olb_closure_set_params(self.h, params)
 
+    def set_conserve(self, mask):
+        """Bit c (0 n, 1 u_x, 2 u_y, 3 T): make that correction mean-free."""
+        olb_closure_set_conserve(self.h, mask)
+
     def get_params(self):
         return olb_closure_get_params(self.h)
 
@@ -607,3 +624,9 @@ class Closure:
 
     def apply(self, lattice):
         return olb_closure_apply(self.h, lattice.h)
+
+    def nudge(self, lattice, target, moments_out=None):
+        """Set the lattice's moments to ``target`` keeping its non-equilibrium
+        part; its previous moments go to ``moments_out`` if given."""
+        out = self._planes(moments_out) if moments_out is not None else None
+        return olb_closure_nudge(self.h, lattice.h, self._planes(target), out)

@@ -180,3 +180,17 @@ def test_correction_moves_moments_by_dm_and_skips_inadmissible():
     np.testing.assert_allclose(m2[3][ok], target[3][ok], rtol=1e-12)
     same, _ = cnn.apply_correction(f, m, np.zeros_like(dm), params["b"], oracle.feq)
     np.testing.assert_allclose(same, f, rtol=1e-15, atol=1e-15)
+
+
+def test_conservative_projection_zeroes_channel_totals():
+    params, m, ref, norm = _net_inputs(nx=6, ny=5, seed=12)
+    raw = cnn.correction(params, m, norm)
+    for mask in (1, 7, 15):
+        dm = cnn.correction(params, m, norm, conserve_mask=mask)
+        for c in range(4):
+            if (mask >> c) & 1:
+                assert abs(dm[c].sum()) <= 1e-12 * np.abs(dm[c]).sum()
+                # only the uniform part is removed
+                np.testing.assert_allclose(dm[c] - raw[c], (dm[c] - raw[c]).mean(), rtol=0, atol=1e-15)
+            else:
+                np.testing.assert_array_equal(dm[c], raw[c])

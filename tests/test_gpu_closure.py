@@ -72,24 +72,29 @@ def test_restriction_rejects_bad_sizes():
         olb.olb_restrict(f.data_ptr(), 10, 8, 4, f.data_ptr(), 0)
 
 
-@pytest.mark.parametrize("shape", [(37, 23), (64, 32), (5, 3)])
-def test_forward_matches_oracle(shape):
+@pytest.mark.parametrize("shape,mask", [((37, 23), 0), ((64, 32), 0), ((5, 3), 0), ((37, 23), 7),
+                                        ((20, 12), 15)])
+def test_forward_matches_oracle(shape, mask):
     torch, olb = _env()
     nx, ny = shape
     params, m, _, norm = _setup(nx, ny)
     c = olb.Closure(nx, ny)
     c.set_norm(*norm)
     c.set_params(params)
+    c.set_conserve(mask)
     delta = torch.empty(4 * nx * ny, dtype=torch.float64, device="cuda:0")
     c.forward(_dev(torch, m), delta)
     torch.cuda.synchronize()
     got = delta.cpu().numpy().reshape(4, ny, nx)
-    mirrored = cnn.correction(params, m, norm, bf16_mirror=True)
-    exact = cnn.correction(params, m, norm, bf16_mirror=False)
+    mirrored = cnn.correction(params, m, norm, bf16_mirror=True, conserve_mask=mask)
+    exact = cnn.correction(params, m, norm, bf16_mirror=False, conserve_mask=mask)
+    for ch in range(4):
+        if (mask >> ch) & 1:
+            assert abs(got[ch].mean()) <= 1e-12 * np.abs(got[ch]).max()
     e_m, e_x = _rel_l2(got, mirrored), _rel_l2(got, exact)
     scale = np.abs(mirrored).max()
     e_max = np.abs(got - mirrored).max() / scale
-    print(f"[closure] forward {shape}: rel-L2 vs bf16-mirrored {e_m:.2e} (max {e_max:.2e}), "
+    print(f"[closure] forward {shape} mask {mask}: rel-L2 vs bf16-mirrored {e_m:.2e} (max {e_max:.2e}), "
           f"vs FP64 {e_x:.2e}", flush=True)
     assert e_m < 1e-3 and e_max < 1e-2
     assert e_x < 3e-2
@@ -164,6 +169,7 @@ def test_constant_correction_matches_oracle_and_restarts(precision):
     c = olb.Closure(nx, ny)
     c.set_norm(np.zeros(4), np.ones(4), np.ones(4))
     c.set_params(params)
+    c.set_conserve(0)           # a uniform correction of every moment
     skipped = c.apply(lat)
     assert skipped == 0
     dm = np.broadcast_to(b3.astype(np.float64)[:, None, None], m0.shape)
@@ -202,6 +208,7 @@ def test_correction_skips_inadmissible_nodes():
     c = olb.Closure(nx, ny)
     c.set_norm(np.zeros(4), np.ones(4), np.ones(4))
     c.set_params(params)
+    c.set_conserve(0)
     skipped = c.apply(lat)
     dm = np.zeros_like(m0)
     dm[0] = float(dn)
@@ -211,6 +218,23 @@ def test_correction_skips_inadmissible_nodes():
     got = lat.get_f()
     np.testing.assert_array_equal(got[:, mask], f0[:, mask])
     assert np.abs(got - want).max() / np.abs(want).max() < 1e-13
+
+
+def test_conservative_apply_keeps_total_mass():
+    torch, olb = _env()
+    cp, lat = _coarse_lattice(olb, 0)
+    nx, ny = cp["nx"], cp["ny"]
+    m0 = np.stack(lat.moments())
+    params, _, _, _ = _setup(nx, ny, seed=13)
+    c = olb.Closure(nx, ny)
+    c.set_norm(m0.mean(axis=(1, 2)), m0.std(axis=(1, 2)), np.array([1e-3, 1e-4, 1e-4, 1e-4]))
+    c.set_params(params)        # default projection: n, u_x, u_y mean-free
+    assert c.apply(lat) == 0
+    m1 = np.stack(lat.moments())
+    print(f"[closure] mass before {m0[0].sum():.15e} after {m1[0].sum():.15e}; "
+          f"max |dn| {np.abs(m1[0] - m0[0]).max():.2e}", flush=True)
+    assert np.abs(m1[0] - m0[0]).max() > 1e-5          # the correction did something
+    assert abs(m1[0].sum() - m0[0].sum()) <= 1e-13 * m0[0].sum()
 
 
 def test_closure_state_errors():
@@ -245,3 +269,51 @@ def test_set_fields_device_matches_host_and_checks_domain():
         b.set_fields_device(_dev(torch, bad))
     assert e.value.code == olb.OLB_E_DOMAIN
     np.testing.assert_array_equal(a.get_f(), b.get_f())   # previous state kept
+
+
+def test_trained_closure_gains_over_the_plain_coarse_run():
+    """Trains the network on the GPU from 12 fine/coarse trajectories and
+    judges it on a held-out sample against the restricted fine run:
+    after training on nudged pairs, per window through the solver; after one
+    round of data aggregation over its own runs, along a free corrected run
+    (better in the first windows, bounded later)."""
+    torch, olb = _env()
+    from paper_1702_01690_amd import closure as C
+    nf, windows = 128, 10
+    refs, cps = [], []
+    for seed in range(5000, 5012):
+        s = I.closure_sample(nf, seed=seed)
+        cps.append(I.coarse_params(s.params))
+        refs.append(C.fine_references(s.params, s.fields, cps[-1], windows))
+    net = olb.Closure(nf // 4, nf // 4)
+    X = torch.cat([C.nudged_inputs(r, cp, net) for r, cp in zip(refs, cps)])
+    R = torch.cat([r[1:] for r in refs])
+    net.set_norm(*C.normalisation(X, R))
+    net.set_params(I.closure_params(seed=7))
+    h = C.train(net, X, R, epochs=30, lr=3e-3, final_lr=3e-4, seed=1)
+    print(f"[closure] {X.shape[0]} nudged pairs; loss {h[0]:.3e} -> {h[-1]:.3e}", flush=True)
+    assert h[-1] < 0.6 * h[0]
+
+    held = I.closure_sample(nf, seed=6000)
+    cp = I.coarse_params(held.params)
+    href = C.fine_references(held.params, held.fields, cp, windows)
+    plain, fixed = C.window_errors(href, cp, net)
+    rp, rf = np.mean([r for _, r in plain]), np.mean([r for _, r in fixed])
+    mp, mf = np.mean([m for m, _ in plain]), np.mean([m for m, _ in fixed])
+    print(f"[closure] per-window density error, mean over windows: rms {rp:.3e} -> {rf:.3e}, "
+          f"max {mp:.3e} -> {mf:.3e}", flush=True)
+    assert rf < 0.85 * rp and mf < mp
+
+    X = torch.cat([X] + [C.rollout_inputs(r, cp_, net) for r, cp_ in zip(refs, cps)])
+    R = torch.cat([R, R])
+    h = C.train(net, X, R, epochs=15, lr=1e-3, final_lr=1e-4, seed=2)
+    print(f"[closure] aggregation: {X.shape[0]} pairs, loss {h[0]:.3e} -> {h[-1]:.3e}", flush=True)
+    roll_p, _ = C.rollout_errors(href, cp, None)
+    roll_f, skipped = C.rollout_errors(href, cp, net)
+    print("[closure] free run (max/rms per window) plain:   " + " ".join(f"{a:.2e}/{b:.1e}" for a, b in roll_p),
+          flush=True)
+    print("[closure] free run (max/rms per window) closure: " + " ".join(f"{a:.2e}/{b:.1e}" for a, b in roll_f),
+          flush=True)
+    assert skipped == 0
+    assert roll_f[0][1] < 0.85 * roll_p[0][1] and roll_f[0][0] < 0.85 * roll_p[0][0]
+    assert max(b for _, b in roll_f) < 1.3 * max(b for _, b in roll_p)

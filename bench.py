@@ -138,7 +138,8 @@ def main():
     ap.add_argument("--graph", type=int, default=10, help="RK3 steps per HIP graph (batches)")
     ap.add_argument("--autotune", action="store_true", help="pick the tile height by trial (batches)")
     ap.add_argument("--tile", type=int, default=8, choices=[8, 16])
-    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--cpu-steps", type=int, default=2000,
+                    help="oracle steps of the CPU-baseline sample (about 10-20 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a device copy of this many GiB (counter calibration)")
@@ -222,7 +223,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.workload, args.cpu_steps if args.workload == "wave2048" else 40)
+        cpu = cpu_baseline(args.workload, args.cpu_steps)
 
     out = {
         "metric": "MLUPS per full RK3 step (D2Q25)",

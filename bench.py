@@ -64,7 +64,14 @@ WORKLOADS = {
                     "n=3.5(1+-1% noise), tau=0.005, dt=2e-4, ds=1/320",
     "channels": "256 walled channels (nx 64..512, ny 128..1024, 43.6 M nodes), FP32-mixed, "
                 "T_w in [0.7, 0.95] T_c, one launch per stage over all channels, graphs of 10 steps",
+    "closure": "learned closure: coarse 512x512 FP32-mixed (ds 1/80, dt 8e-4) corrected every 10 steps "
+               "by the bf16 conv net, against fine 2048x2048 FP64 (ds 1/320, dt 2e-4); spinodal at "
+               "T in [0.75, 0.95] T_c, n = 3.5(1 +- 1% noise), tau = 0.005; 200 coarse steps",
 }
+# bf16 dense matrix-core peak of one MI355X
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# network flops per node and forward pass: 2 x (36 x 32 + 288 x 32 + 288 x 4) MACs
+CLOSURE_FLOPS_PER_NODE = 2 * (36 * 32 + 288 * 32 + 288 * 4)
 
 
 def make_cases(workload):
@@ -129,6 +136,100 @@ def copy_kernel(gib, reps=10):
                       "copy_GBps": round(moved / secs / 1e9, 1), "reps": reps}))
 
 
+def run_closure(args):
+    """Learned-closure workload: trains the network on the GPU from solver
+    pairs (fine 512^2 -> coarse 128^2; the network is local, so its weights
+    carry over to any lattice size), then runs the 2048^2 / 512^2 pair."""
+    import torch
+    import olb_inputs as I
+    from paper_1702_01690_amd import olb, closure as C
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    nf_train, nf, factor, window, horizon = 512, 2048, 4, 10, 200
+    samples = []
+    for seed in range(5000, 5000 + args.closure_samples):
+        s = I.closure_sample(nf_train, seed=seed)
+        samples.append((s.params, s.fields))
+    small = olb.Closure(nf_train // factor, nf_train // factor)
+    t0 = time.perf_counter()
+    info = C.train_closure(samples, I.coarse_params, small, windows=8, window=window, epochs=args.closure_epochs,
+                           rounds=1, round_epochs=max(1, args.closure_epochs // 2),
+                           init_params=I.closure_params(seed=7), seed=1, log=log)
+    t_train = time.perf_counter() - t0
+    del samples
+    log(f"trained on {info['pairs']} pairs in {t_train:.1f} s")
+
+    held = I.closure_sample(nf, seed=6000)
+    cp = I.coarse_params(held.params)
+    net = olb.Closure(nf // factor, nf // factor)
+    net.set_norm(*info["norm"])
+    net.set_params(small.get_params())
+    refs = C.fine_references(held.params, held.fields, cp, horizon // window, window, factor)
+    plain_w, fixed_w = C.window_errors(refs, cp, net, window)
+    roll_p, _ = C.rollout_errors(refs, cp, None, window)
+    roll_f, skipped = C.rollout_errors(refs, cp, net, window)
+    log("free run max/rms per window, plain:   " + " ".join(f"{a:.2e}/{b:.1e}" for a, b in roll_p))
+    log("free run max/rms per window, closure: " + " ".join(f"{a:.2e}/{b:.1e}" for a, b in roll_f))
+
+    t_fine, t_closure = C.timing(held.params, held.fields, cp, net, horizon, window, factor)
+    _, t_plain = C.timing(held.params, held.fields, cp, None, horizon, window, factor)
+
+    # the network's forward pass, timed with events on the closure's stream
+    P = (nf // factor) ** 2
+    X = refs[1].clone()
+    delta = torch.empty_like(X)
+    net.forward(X, delta)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 50
+    ev0.record(net.stream)
+    for _ in range(reps):
+        net.forward(X, delta)
+    ev1.record(net.stream)
+    torch.cuda.synchronize()
+    fwd_s = ev0.elapsed_time(ev1) / 1e3 / reps
+    fwd_tflops = CLOSURE_FLOPS_PER_NODE * P / fwd_s / 1e12
+
+    fine_updates = nf * nf * horizon * factor
+    mean = lambda xs: float(np.mean(xs))
+    out = {
+        "metric": "MLUPS per full RK3 step (D2Q25)",
+        "value": round(fine_updates / t_closure / 1e6, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": horizon,
+        "warmup": 2,
+        "ms_per_step": round(t_closure / horizon * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64 solver, bf16 net",
+        "data": "synthetic",
+        "config": {"workload": "closure", "description": WORKLOADS["closure"],
+                   "value_is": "fine-lattice-equivalent updates per second (2048^2 x 4 fine steps per coarse step)",
+                   "fine_fp64_mlups": round(fine_updates / t_fine / 1e6, 2),
+                   "speedup_vs_fine_fp64": round(t_fine / t_closure, 2),
+                   "speedup_plain_coarse": round(t_fine / t_plain, 2),
+                   "training": {"pairs": info["pairs"], "seconds": round(t_train, 1),
+                                "loss_first_last": [info["history"][0][0], info["history"][-1][-1]]},
+                   "density_error_vs_fine": {
+                       "per_window_mean_max": [mean([m for m, _ in plain_w]), mean([m for m, _ in fixed_w])],
+                       "per_window_mean_rms": [mean([r for _, r in plain_w]), mean([r for _, r in fixed_w])],
+                       "free_run_first_window_max": [roll_p[0][0], roll_f[0][0]],
+                       "free_run_end_max": [roll_p[-1][0], roll_f[-1][0]],
+                       "free_run_end_rms": [roll_p[-1][1], roll_f[-1][1]],
+                       "order": "[plain coarse, coarse + closure]", "skipped_nodes": skipped}},
+        "roofline": {"bound": "mfma", "kernel": "network forward (3 bf16 implicit-GEMM convolutions)",
+                     "achieved": round(fwd_tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(fwd_tflops / MFMA_BF16_PEAK_TFLOPS, 5), "traffic": None,
+                     "forward_ms": round(fwd_s * 1e3, 4)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +242,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2000,
                     help="oracle steps of the CPU-baseline sample (about 10-20 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--closure-samples", type=int, default=64,
+                    help="training trajectories of the closure workload (8 pairs each)")
+    ap.add_argument("--closure-epochs", type=int, default=30)
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -151,6 +255,10 @@ def main():
         print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it "
               "(see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "closure":
+        run_closure(args)
+        return
 
     import torch
     from paper_1702_01690_amd import olb

@@ -139,14 +139,15 @@ def train_closure(samples, coarse_params_of, net, windows=8, window=10, factor=4
     Nudged pairs first, then ``rounds`` rounds of data aggregation over the
     network's own runs.  Sets the normalisation and the parameters of
     ``net`` (init_params: float32 vector).  Returns the loss histories, the
-    pair count and the fine references (for evaluation)."""
+    pair count and the normalisation."""
     torch = _torch()
     cps = [coarse_params_of(fp) for fp, _ in samples]
     refs = [fine_references(fp, fl, cp, windows, window, factor, device)
             for (fp, fl), cp in zip(samples, cps)]
     X = torch.cat([nudged_inputs(r, cp, net, window, device) for r, cp in zip(refs, cps)])
     R = torch.cat([r[1:] for r in refs])
-    net.set_norm(*normalisation(X, R))
+    norm = normalisation(X, R)
+    net.set_norm(*norm)
     if init_params is not None:
         net.set_params(init_params)
     hist = [train(net, X, R, epochs, lr, lr / 10, seed, log)]
@@ -159,7 +160,7 @@ def train_closure(samples, coarse_params_of, net, windows=8, window=10, factor=4
         hist.append(train(net, X, R, round_epochs, round_lr, round_lr / 10, seed + 1 + k))
         if log:
             log(f"aggregation round {k + 1}: {X.shape[0]} pairs, loss {hist[-1][0]:.3e} -> {hist[-1][-1]:.3e}")
-    return dict(history=hist, pairs=int(X.shape[0]))
+    return dict(history=hist, pairs=int(X.shape[0]), norm=norm)
 
 
 def _err(m, ref):

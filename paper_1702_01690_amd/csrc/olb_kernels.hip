@@ -43,55 +43,57 @@ __device__ __forceinline__ float frcp(float d) { return __builtin_amdgcn_rcpf(d)
 // No epsilon: when indicators vanish, the weights follow Tab. weno, i.e. the
 // ideal weights restricted to the vanishing candidates.  Indicators are formed
 // from first differences d, so a vanishing indicator is exactly "three equal
-// values".  The unnormalised weights use a single reciprocal,
+// values".  The weights are scale free, so each indicator is used times 4:
+// s_q = (13/3) a_q^2 + b_q^2.  The unnormalised weights use one reciprocal,
 //   w_q ~ delta_q prod_{r != q} s_r^2,  with delta scaled to (1, 6, 3),
-// and the three candidates enter as one combination of the d's:
-//   sum_q w_q (F^q - f_i) = [-2 w1 d1 + (5 w1 + w2) d2 + (2 w2 + 4 w3) d3 - w3 d4] / 6.
+// which already gives Tab. weno when one indicator vanishes (that candidate
+// alone keeps a non-zero weight).  When two or more vanish, every candidate
+// that keeps a weight equals f_i (its values are all f_i), so the result is
+// f_i.  The candidates enter through their offsets from f_i, times 6:
+//   e1 = 5 d2 - 2 d1,  e2 = d2 + 2 d3,  e3 = 4 d3 - d4.
 __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, double v3, double v4) {
   const double d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
-  const double a1 = d2 - d1, b1 = 3.0 * d2 - d1;
+  const double a1 = d2 - d1, b1 = __builtin_fma(3.0, d2, -d1);
   const double a2 = d3 - d2, b2 = d2 + d3;
-  const double a3 = d4 - d3, b3 = 3.0 * d3 - d4;
-  const double s1 = (13.0 / 12.0) * a1 * a1 + 0.25 * b1 * b1;
-  const double s2 = (13.0 / 12.0) * a2 * a2 + 0.25 * b2 * b2;
-  const double s3 = (13.0 / 12.0) * a3 * a3 + 0.25 * b3 * b3;
+  const double a3 = d4 - d3, b3 = __builtin_fma(3.0, d3, -d4);
+  const double s1 = __builtin_fma(a1 * (13.0 / 3.0), a1, b1 * b1);
+  const double s2 = __builtin_fma(a2 * (13.0 / 3.0), a2, b2 * b2);
+  const double s3 = __builtin_fma(a3 * (13.0 / 3.0), a3, b3 * b3);
   const double q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
-  double w1 = q2 * q3, w2 = 6.0 * (q1 * q3), w3 = 3.0 * (q1 * q2);
-  const bool z1 = s1 == 0.0, z2 = s2 == 0.0, z3 = s3 == 0.0;
-  if (z1 | z2 | z3) {
-    w1 = z1 ? 1.0 : 0.0;
-    w2 = z2 ? 6.0 : 0.0;
-    w3 = z3 ? 3.0 : 0.0;
-  }
-  const double num = (5.0 * w1 + w2) * d2 - 2.0 * w1 * d1 + (2.0 * w2 + 4.0 * w3) * d3 - w3 * d4;
-  return v2 + num * frcp(6.0 * (w1 + w2 + w3));
+  const double w1 = q2 * q3, w2 = 6.0 * (q1 * q3), w3 = 3.0 * (q1 * q2);
+  const double e1 = __builtin_fma(5.0, d2, -2.0 * d1);
+  const double e2 = __builtin_fma(2.0, d3, d2);
+  const double e3 = __builtin_fma(4.0, d3, -d4);
+  const double num = __builtin_fma(w1, e1, __builtin_fma(w2, e2, w3 * e3));
+  const double den = w1 + w2 + w3;
+  const double r = __builtin_fma(num, frcp(6.0 * den), v2);
+  return den == 0.0 ? v2 : r;
 }
 
-// FP32 variant: the weights are invariant under scaling of f, so the first
-// differences are normalised by their largest magnitude before squaring; this
-// keeps s^4 products inside the single-precision range.  A product that still
-// underflows is treated as a vanishing indicator.
+// FP32: the differences are first divided by their largest magnitude (the
+// weights are scale invariant) so that the products of squared indicators stay
+// in range; an indicator product that still underflows acts as a vanishing
+// one, which changes the result by far less than FP32 rounding.
 __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3, float v4) {
   float d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
   const float m = fmaxf(fmaxf(fabsf(d1), fabsf(d2)), fmaxf(fabsf(d3), fabsf(d4)));
   const float im = m > 0.0f ? frcp(m) : 0.0f;
   d1 *= im; d2 *= im; d3 *= im; d4 *= im;
-  const float a1 = d2 - d1, b1 = 3.0f * d2 - d1;
+  const float a1 = d2 - d1, b1 = __builtin_fmaf(3.0f, d2, -d1);
   const float a2 = d3 - d2, b2 = d2 + d3;
-  const float a3 = d4 - d3, b3 = 3.0f * d3 - d4;
-  const float s1 = (13.0f / 12.0f) * a1 * a1 + 0.25f * b1 * b1;
-  const float s2 = (13.0f / 12.0f) * a2 * a2 + 0.25f * b2 * b2;
-  const float s3 = (13.0f / 12.0f) * a3 * a3 + 0.25f * b3 * b3;
+  const float a3 = d4 - d3, b3 = __builtin_fmaf(3.0f, d3, -d4);
+  const float s1 = __builtin_fmaf(a1 * (13.0f / 3.0f), a1, b1 * b1);
+  const float s2 = __builtin_fmaf(a2 * (13.0f / 3.0f), a2, b2 * b2);
+  const float s3 = __builtin_fmaf(a3 * (13.0f / 3.0f), a3, b3 * b3);
   const float q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
-  float w1 = q2 * q3, w2 = 6.0f * (q1 * q3), w3 = 3.0f * (q1 * q2);
-  const bool z1 = q1 == 0.0f, z2 = q2 == 0.0f, z3 = q3 == 0.0f;
-  if (z1 | z2 | z3) {
-    w1 = z1 ? 1.0f : 0.0f;
-    w2 = z2 ? 6.0f : 0.0f;
-    w3 = z3 ? 3.0f : 0.0f;
-  }
-  const float num = (5.0f * w1 + w2) * d2 - 2.0f * w1 * d1 + (2.0f * w2 + 4.0f * w3) * d3 - w3 * d4;
-  return v2 + m * (num * frcp(6.0f * (w1 + w2 + w3)));
+  const float w1 = q2 * q3, w2 = 6.0f * (q1 * q3), w3 = 3.0f * (q1 * q2);
+  const float e1 = __builtin_fmaf(5.0f, d2, -2.0f * d1);
+  const float e2 = __builtin_fmaf(2.0f, d3, d2);
+  const float e3 = __builtin_fmaf(4.0f, d3, -d4);
+  const float num = __builtin_fmaf(w1, e1, __builtin_fmaf(w2, e2, w3 * e3));
+  const float den = w1 + w2 + w3;
+  const float r = __builtin_fmaf(m, num * frcp(6.0f * den), v2);
+  return den == 0.0f ? v2 : r;
 }
 
 // Moment sums of one node: n = sum f, j = sum p f, e = sum |p|^2 f.  With the

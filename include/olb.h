@@ -133,6 +133,11 @@ olb_status olb_wall_density(olb_ctx* c, double* nw_lo, double* nw_hi);
 /* Block height of the stage kernel: 8 (default) or 16 waves per workgroup;
  * each workgroup updates 63 x (by - 1) nodes.  Results do not depend on it. */
 olb_status olb_set_tile(olb_ctx* c, int32_t by);
+/* Order in which the stage launch visits the tiles: 0 = rows of the tile
+ * grid; W > 0 = vertical strips W tiles wide, visited left to right, rows
+ * within a strip (tiles that run together then share halos in L2).  Results
+ * do not depend on it (bitwise).  OLB_E_ARG outside 0..1024. */
+olb_status olb_set_tile_order(olb_ctx* c, int32_t strip);
 
 /* Number of stage-kernel launches olb_step enqueues per RK-3 step (3), and
  * of wall-ghost launches (3 with walls, else 0). */
@@ -172,6 +177,7 @@ olb_status olb_batch_wall_density(olb_batch* b, int32_t i, double* nw_lo, double
  * non-default stream.  Results are bitwise those of direct launches. */
 olb_status olb_batch_use_graph(olb_batch* b, int32_t steps_per_graph);
 olb_status olb_batch_set_tile(olb_batch* b, int32_t by);
+olb_status olb_batch_set_tile_order(olb_batch* b, int32_t strip);
 /* Choose the stage tile height (8 or 16) by timing trial_steps steps of each
  * on a uniform rest state of every instance; the choice is read from / added
  * to the JSON file cache_path (NULL: no cache).  The trial overwrites the

@@ -51,6 +51,8 @@ struct BatchArgs {
   int stage;            // 0, 1, 2: f_src = f[stage], f_dst = f[(stage + 1) % 3]
   int cur;              // carry[cur] belongs to f_src
   int* flag;            // set to 1 when a non-finite density is produced
+  int strip;            // tile order: 0 = rows of the tile grid; W > 0 = strips
+                        // W tiles wide, rows within a strip, strips left to right
   double A, B;          // f_dst = A f^n + B (f_src + dt L[f_src])
 };
 

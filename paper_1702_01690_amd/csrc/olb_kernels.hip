@@ -200,6 +200,25 @@ struct StageLds {
 };
 
 // One 64 x BY tile (origin x0, y0) of one RK stage.
+#ifndef OLB_PREFETCH64
+#define OLB_PREFETCH64 4
+#endif
+#ifndef OLB_PREFETCH32
+#define OLB_PREFETCH32 4
+#endif
+// population planes in flight: plane ti is in LDS, ti + 1 .. ti + PREFETCH - 1
+// are being loaded into registers (deeper gains nothing measurable)
+// FP32 stage: ask for 6 waves per SIMD (three 8-wave workgroups per CU); the
+// register budget of 80 costs a 48-byte spill outside the population loop and
+// still runs 8 % faster than 5 waves without it.  FP64 needs ~120 registers.
+#ifndef OLB_WAVES32
+#define OLB_WAVES32 6
+#endif
+template <typename Real>
+constexpr int min_waves_per_simd() { return std::is_same<Real, float>::value ? OLB_WAVES32 : 1; }
+template <typename Real>
+constexpr int prefetch_depth() { return std::is_same<Real, float>::value ? OLB_PREFETCH32 : OLB_PREFETCH64; }
+
 template <typename Real, int BY, bool WALLS>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, const int y0,
                                            StageLds<Real, BY>& sm) {
@@ -328,7 +347,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   // population order of the 24 planes (12 has none); plane t lives in buffer
   // t & 1 and its face-exchange row in fy_sh[t & 1]
   auto tile_pop = [](int t) { return t < 12 ? t : t + 1; };
-  Real pre[SLOTS];
+  // planes ti + 1 .. ti + PREFETCH - 1 are in flight in registers while
+  // plane ti is used (ring of PREFETCH - 1 slots)
+  constexpr int PF = prefetch_depth<Real>() - 1;
+  Real pre[PF][SLOTS];
   {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -336,7 +358,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       if (i < TN) pl0[i] = src[soff[s]];
     }
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) pre[s] = src[1 * ps + soff[s]];
+    for (int j = 1; j <= PF; ++j)
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) pre[j % PF][s] = src[tile_pop(j) * ps + soff[s]];
   }
   __syncthreads();
 
@@ -362,12 +386,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           const int i = tid + s * NT;
-          if (i < TN) Q[i] = pre[s];
+          if (i < TN) Q[i] = pre[(ti + 1) % PF][s];
         }
       }
-      if (ti + 2 < 24) {
+      if (ti + 1 + PF < 24) {
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) pre[s] = src[tile_pop(ti + 2) * ps + soff[s]];
+        for (int s = 0; s < SLOTS; ++s) pre[(ti + 1) % PF][s] = src[tile_pop(ti + 1 + PF) * ps + soff[s]];
       }
       fk = P[ownc];
       Real rxl = 0, ryl = 0;
@@ -466,7 +490,7 @@ __device__ __forceinline__ int find_instance(const InstDesc* inst, int ninst, in
 // rows, whose shared x-halos and the next row's y-halos meet in its L2
 // (measured faster than column-by-column order on 2048^2).
 template <typename Real, int BY, bool WALLS>
-__global__ void __launch_bounds__(64 * BY) stage_kernel(const BatchArgs ba) {
+__global__ void __launch_bounds__(64 * BY, min_waves_per_simd<Real>()) stage_kernel(const BatchArgs ba) {
   __shared__ StageLds<Real, BY> sm;
   const int bid = blockIdx.x;
   const int q8 = ba.total_tiles >> 3, r8 = ba.total_tiles & 7, xcd = bid & 7;
@@ -493,7 +517,21 @@ __global__ void __launch_bounds__(64 * BY) stage_kernel(const BatchArgs ba) {
   a.B = ba.B;
   a.rho0 = d.rho0;
   const int local = t - d.tile_base;
-  const int tile_y = local / d.tiles_x, tile_x = local - tile_y * d.tiles_x;
+  int tile_x, tile_y;
+  if (ba.strip > 0 && ba.strip < d.tiles_x) {
+    // strips of ba.strip tile columns (the last one may be narrower), rows
+    // within a strip: tiles that start together share their halo rows and
+    // columns while those are still in L2
+    const int per = ba.strip * d.tiles_y;
+    const int s = local / per;
+    const int w = min(ba.strip, d.tiles_x - s * ba.strip);
+    const int r = local - s * per;
+    tile_y = r / w;
+    tile_x = s * ba.strip + (r - tile_y * w);
+  } else {
+    tile_y = local / d.tiles_x;
+    tile_x = local - tile_y * d.tiles_x;
+  }
   stage_tile<Real, BY, WALLS>(a, tile_x * TILE_X, tile_y * (BY - 1), sm);
 }
 

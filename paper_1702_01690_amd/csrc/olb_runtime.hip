@@ -108,6 +108,7 @@ struct Engine {
   int rb = 8;
   bool walls = false;
   int by = 8;
+  int strip = 0;                   // tile order (BatchArgs::strip)
   int cur = 0;                     // carry index of the current f^n
   int total_tiles = 0, wall_blocks = 0;
   int graph_steps = 0;             // 0: direct launches
@@ -373,6 +374,7 @@ struct Engine {
       ba.stage = s;
       ba.cur = cur;
       ba.flag = flag;
+      ba.strip = strip;
       ba.A = olbc::RK_A[s];
       ba.B = olbc::RK_B[s];
       olb_status e = hip(olbk::launch_stage(ba, rb, by, walls, stream), "stage kernel");
@@ -416,6 +418,14 @@ struct Engine {
       olb_status s = enqueue_step();
       if (s) return s;
     }
+    return OLB_OK;
+  }
+
+  olb_status set_tile_order(int32_t w) {
+    if (w < 0 || w > 1024) return fail(OLB_E_ARG, "strip width must be in 0..1024 tiles");
+    if (w == strip) return OLB_OK;
+    strip = w;
+    drop_graph();
     return OLB_OK;
   }
 
@@ -646,6 +656,7 @@ olb_status olb_wall_density(olb_ctx* c, double* lo, double* hi) {
   return c ? c->e.wall_density(0, lo, hi) : OLB_E_ARG;
 }
 olb_status olb_set_tile(olb_ctx* c, int32_t by) { return c ? c->e.set_tile(by) : OLB_E_ARG; }
+olb_status olb_set_tile_order(olb_ctx* c, int32_t strip) { return c ? c->e.set_tile_order(strip) : OLB_E_ARG; }
 olb_status olb_launch_counts(const olb_ctx* c, int32_t* stage, int32_t* walls) {
   if (!c || !stage || !walls) return OLB_E_ARG;
   *stage = 3;
@@ -714,6 +725,9 @@ olb_status olb_batch_use_graph(olb_batch* b, int32_t steps_per_graph) {
   return OLB_OK;
 }
 olb_status olb_batch_set_tile(olb_batch* b, int32_t by) { return b ? b->e.set_tile(by) : OLB_E_ARG; }
+olb_status olb_batch_set_tile_order(olb_batch* b, int32_t strip) {
+  return b ? b->e.set_tile_order(strip) : OLB_E_ARG;
+}
 olb_status olb_batch_autotune(olb_batch* b, int32_t trial_steps, const char* cache_path,
                               int32_t* chosen_by) {
   return b ? b->e.autotune(trial_steps, cache_path, chosen_by) : OLB_E_ARG;

@@ -64,6 +64,8 @@ _SIGS = {
     "olb_set_f": ([_vp, _dp], ctypes.c_int),
     "olb_wall_density": ([_vp, _dp, _dp], ctypes.c_int),
     "olb_set_tile": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "olb_set_tile_order": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "olb_batch_set_tile_order": ([_vp, ctypes.c_int32], ctypes.c_int),
     "olb_launch_counts": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "olb_last_error": ([_vp], ctypes.c_char_p),
     "olb_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -198,6 +200,10 @@ def olb_set_tile(h, by):
     _check(lib().olb_set_tile(h, int(by)), h)
 
 
+def olb_set_tile_order(h, strip):
+    _check(lib().olb_set_tile_order(h, int(strip)), h)
+
+
 def olb_launch_counts(h):
     s, w = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().olb_launch_counts(h, ctypes.byref(s), ctypes.byref(w)), h)
@@ -284,6 +290,9 @@ class Lattice:
     def set_tile(self, by):
         olb_set_tile(self.h, by)
 
+    def set_tile_order(self, strip):
+        olb_set_tile_order(self.h, strip)
+
     def launch_counts(self):
         return olb_launch_counts(self.h)
 
@@ -362,6 +371,10 @@ def olb_batch_use_graph(h, steps_per_graph):
 
 def olb_batch_set_tile(h, by):
     _check(lib().olb_batch_set_tile(h, int(by)), h, True)
+
+
+def olb_batch_set_tile_order(h, strip):
+    _check(lib().olb_batch_set_tile_order(h, int(strip)), h, True)
 
 
 def olb_batch_autotune(h, trial_steps, cache_path=None):
@@ -455,6 +468,9 @@ class Batch:
 
     def set_tile(self, by):
         olb_batch_set_tile(self.h, by)
+
+    def set_tile_order(self, strip):
+        olb_batch_set_tile_order(self.h, strip)
 
     def autotune(self, trial_steps=3, cache_path=None):
         return olb_batch_autotune(self.h, trial_steps, cache_path)

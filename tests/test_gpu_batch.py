@@ -112,6 +112,17 @@ def test_graph_replays_match_eager_launches(by):
     np.testing.assert_array_equal(g.get_f(1), e.get_f(1))
 
 
+def test_batch_tile_order_does_not_change_results():
+    cases = _channels()
+    a = _batch(cases)
+    b = _batch(cases)
+    b.set_tile_order(2)
+    a.step(5)
+    b.step(5)
+    for i in range(len(cases)):
+        np.testing.assert_array_equal(a.get_f(i), b.get_f(i))
+
+
 def test_autotune_picks_a_tile_and_caches_it(tmp_path):
     olb = _olb()
     cases = _channels()

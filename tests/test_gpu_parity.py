@@ -172,6 +172,29 @@ def test_tile_height_does_not_change_results():
     np.testing.assert_array_equal(fa, fb)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tile_order_does_not_change_results(precision):
+    """Strips of 1, 2 and 5 tile columns (150 nodes = 3 tile columns, so a
+    2-wide strip leaves a narrower last one) and a wider-than-grid strip
+    visit every tile once."""
+    from paper_1702_01690_amd import olb
+    case = _noisy_vdw(150, 37)
+    case.params["precision"] = precision
+    case.params["rho_ref"] = 1.0
+    ref = None
+    for strip in (0, 1, 2, 5, 64):
+        lat = olb.Lattice(case.params)
+        lat.set_tile_order(strip)
+        lat.set_fields(*case.fields)
+        lat.step(4)
+        f = lat.get_f()
+        if ref is None:
+            ref = f
+        np.testing.assert_array_equal(f, ref, err_msg=f"strip {strip}")
+    with pytest.raises(olb.OlbError):
+        lat.set_tile_order(-1)
+
+
 def test_checkpoint_restart_is_bitwise():
     olb = _olb()
     case = CASES["channel67x20"]()

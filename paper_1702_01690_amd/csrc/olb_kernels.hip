@@ -214,8 +214,11 @@ struct StageLds {
 #ifndef OLB_WAVES32
 #define OLB_WAVES32 6
 #endif
+#ifndef OLB_WAVES64
+#define OLB_WAVES64 1
+#endif
 template <typename Real>
-constexpr int min_waves_per_simd() { return std::is_same<Real, float>::value ? OLB_WAVES32 : 1; }
+constexpr int min_waves_per_simd() { return std::is_same<Real, float>::value ? OLB_WAVES32 : OLB_WAVES64; }
 template <typename Real>
 constexpr int prefetch_depth() { return std::is_same<Real, float>::value ? OLB_PREFETCH32 : OLB_PREFETCH64; }
 

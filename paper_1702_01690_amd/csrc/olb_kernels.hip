@@ -185,6 +185,17 @@ __device__ __forceinline__ void carry_finish(double n, double jx, double jy, dou
 // --------------------------------------------------------------------------
 
 // LDS of one stage workgroup.
+#ifndef OLB_GROUP64
+#define OLB_GROUP64 1
+#endif
+#ifndef OLB_GROUP32
+#define OLB_GROUP32 2
+#endif
+// populations per LDS barrier in the stage loop: two for FP32 (+2 %), one for
+// FP64 (two cost 6 registers and 2 %)
+template <typename Real>
+constexpr int pop_group() { return std::is_same<Real, float>::value ? OLB_GROUP32 : OLB_GROUP64; }
+
 template <typename Real, int BY>
 struct StageLds {
   static constexpr int TW = 69;          // tile columns x0-3 .. x0+65
@@ -192,11 +203,12 @@ struct StageLds {
   static constexpr int TN = TW * TH;
   static constexpr int PB = TN * (int)sizeof(Real);
   static constexpr int MB = TN * (int)sizeof(double);
-  static constexpr int BUF = 2 * (PB > MB ? PB : MB);
-  // two population planes, aliased with the carried (n, Delta p) tile
+  static constexpr int G = pop_group<Real>();
+  static constexpr int BUF = (2 * G * PB > 2 * MB) ? 2 * G * PB : 2 * MB;
+  // 2G population planes, aliased with the carried (n, Delta p) tile
   __attribute__((aligned(16))) unsigned char buf[BUF];
-  // double-buffered row of lower-face reconstructions
-  Real fy[2][BY][64];
+  // double-buffered rows of lower-face reconstructions, one per plane buffer
+  Real fy[2 * G][BY][64];
 };
 
 // One 64 x BY tile (origin x0, y0) of one RK stage.
@@ -231,7 +243,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   constexpr int NT = 64 * BY;
   constexpr int SLOTS = (TN + NT - 1) / NT;
   Real* const pl0 = reinterpret_cast<Real*>(sm.buf);
-  Real* const pl1 = pl0 + TN;
   double* const mn = reinterpret_cast<double*>(sm.buf);
   double* const mp = mn + TN;
   auto& fy_sh = sm.fy;
@@ -347,23 +358,31 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
 
   __syncthreads();  // the macroscopic tile is dead; its LDS becomes the planes
 
-  // population order of the 24 planes (12 has none); plane t lives in buffer
-  // t & 1 and its face-exchange row in fy_sh[t & 1]
-  auto tile_pop = [](int t) { return t < 12 ? t : t + 1; };
-  // planes ti + 1 .. ti + PREFETCH - 1 are in flight in registers while
-  // plane ti is used (ring of PREFETCH - 1 slots)
+  // The 24 planes with a halo (population 12 has none) stream through LDS in
+  // groups of G: while group g is used from buffers (t mod 2G), group g + 1 is
+  // written into the other G buffers and later planes are in flight into
+  // registers (ring of PF slots); one barrier per group.  Per population, the
+  // contributions that do not need the upper face are accumulated before the
+  // barrier, the y-advection after it.
+  constexpr int G = pop_group<Real>();
+  constexpr int NB = 2 * G;
   constexpr int PF = prefetch_depth<Real>() - 1;
+  static_assert(PF >= G, "the register ring must hold the next group");
+  auto tile_pop = [](int t) { return t < 12 ? t : t + 1; };
+  auto plane = [&](int t) { return pl0 + (t % NB) * TN; };
   Real pre[PF][SLOTS];
   {
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int i = tid + s * NT;
-      if (i < TN) pl0[i] = src[soff[s]];
-    }
+    for (int j = 0; j < G; ++j)
 #pragma unroll
-    for (int j = 1; j <= PF; ++j)
+      for (int s = 0; s < SLOTS; ++s) {
+        const int i = tid + s * NT;
+        if (i < TN) plane(j)[i] = src[tile_pop(j) * ps + soff[s]];
+      }
 #pragma unroll
-      for (int s = 0; s < SLOTS; ++s) pre[j % PF][s] = src[tile_pop(j) * ps + soff[s]];
+    for (int t = G; t < G + PF; ++t)
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[tile_pop(t) * ps + soff[s]];
   }
   __syncthreads();
 
@@ -371,33 +390,50 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   const int rowc = (ty + 3) * TW + tx;   // x-face row values start here
   const int colc = ty * TW + tx + 3;     // y-face column values start here
   const int ownc = (ty + 3) * TW + tx + 3;
+  const Real tfac = cb;
+
+  // everything of population k except its y-advection
+  auto local_terms = [&](int k, Real fk) {
+    const int kx = k % 5, ky = k / 5;
+    carry_add(k, (double)fk, sn, sjx, sjy, se);
+    acc[k] += tfac * fk;
+    const Real tfx = cx * fk, tfy = cy * fk;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      acc[5 * ky + i] += (Real)MT.v[i][kx] * tfx;
+      acc[5 * i + kx] += (Real)MT.v[i][ky] * tfy;
+    }
+  };
 
 #pragma unroll
-  for (int k = 0; k < 25; ++k) {
-    const int kx = k % 5, ky = k / 5;
-    const double px = Rk[kx], py = Rk[ky];
-    Real fk, adv = 0;
-    if (k == 12) {
-      fk = f12;
-    } else {
-      const int ti = k < 12 ? k : k - 1;
-      Real* const P = (ti & 1) ? pl1 : pl0;
-      // stage plane ti + 1 (loaded during the previous population) and
-      // start loading plane ti + 2
-      if (ti + 1 < 24) {
-        Real* const Q = (ti & 1) ? pl0 : pl1;
+  for (int t0 = 0; t0 < 24; t0 += G) {
+    if (t0 == 12) local_terms(12, f12);   // population 12 keeps its place in the sums
+    // stage the next group and refill the ring
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int t = t0 + G + j;
+      if (t < 24) {
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           const int i = tid + s * NT;
-          if (i < TN) Q[i] = pre[(ti + 1) % PF][s];
+          if (i < TN) plane(t)[i] = pre[t % PF][s];
+        }
+        if (t + PF < 24) {
+#pragma unroll
+          for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[tile_pop(t + PF) * ps + soff[s]];
         }
       }
-      if (ti + 1 + PF < 24) {
+    }
+    Real advx[G], ryl[G];
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) pre[(ti + 1) % PF][s] = src[tile_pop(ti + 1 + PF) * ps + soff[s]];
-      }
-      fk = P[ownc];
-      Real rxl = 0, ryl = 0;
+    for (int j = 0; j < G; ++j) {
+      const int t = t0 + j, k = tile_pop(t);
+      const int kx = k % 5, ky = k / 5;
+      const double px = Rk[kx], py = Rk[ky];
+      const Real* const P = plane(t);
+      const Real fk = P[ownc];
+      Real rxl = 0;
+      ryl[j] = 0;
       if (kx != 2 && ty < BY - 1) {
         const Real c0 = P[rowc], c1 = P[rowc + 1], c2 = P[rowc + 2], c3 = P[rowc + 3],
                    c4 = P[rowc + 4], c5 = P[rowc + 5];
@@ -407,24 +443,24 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       if (ky != 2) {
         const Real c0 = P[colc], c1 = P[colc + TW], c2 = P[colc + 2 * TW], c3 = P[colc + 3 * TW],
                    c4 = P[colc + 4 * TW], c5 = P[colc + 5 * TW];
-        ryl = py > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
-        fy_sh[ti & 1][ty][tx] = ryl;
+        ryl[j] = py > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
+        fy_sh[t % NB][ty][tx] = ryl[j];
       }
       const Real rxr = (kx != 2) ? __shfl_down(rxl, 1) : (Real)0;
-      __syncthreads();
-      if (kx != 2) adv += (Real)px * (rxr - rxl);
-      if (ky != 2) {
-        const Real ryt = fy_sh[ti & 1][ty < BY - 1 ? ty + 1 : ty][tx];
-        adv += (Real)py * (ryt - ryl);
-      }
+      advx[j] = (kx != 2) ? (Real)px * (rxr - rxl) : (Real)0;
+      local_terms(k, fk);
     }
-    carry_add(k, (double)fk, sn, sjx, sjy, se);
-    acc[k] += cb * fk + cadv * adv;
-    const Real tfx = cx * fk, tfy = cy * fk;
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      acc[5 * ky + i] += (Real)MT.v[i][kx] * tfx;
-      acc[5 * i + kx] += (Real)MT.v[i][ky] * tfy;
+    for (int j = 0; j < G; ++j) {
+      const int t = t0 + j, k = tile_pop(t);
+      const int ky = k / 5;
+      Real adv = advx[j];
+      if (ky != 2) {
+        const Real ryt = fy_sh[t % NB][ty < BY - 1 ? ty + 1 : ty][tx];
+        adv += (Real)Rk[ky] * (ryt - ryl[j]);
+      }
+      acc[k] += cadv * adv;
     }
     // do the updates now: left alone, the compiler sinks them to the end of
     // the kernel and keeps every population's inputs live until then

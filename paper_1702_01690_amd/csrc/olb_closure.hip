@@ -41,10 +41,18 @@ __device__ __forceinline__ bf16 to_bf16(float f) {
 }
 __device__ __forceinline__ float from_bf16(bf16 h) { return __uint_as_float(((unsigned)h) << 16); }
 
-// offsets of the 9 taps (tap = 3 ky + kx, neighbour (x + kx - 1, y + ky - 1))
-__device__ __forceinline__ int tap_pixel(int p, int tap, int nx, int ny) {
-  const int y = p / nx, x = p - y * nx;
-  int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+// pixel coordinates (one division per lane and kernel, not per tap)
+struct Pix {
+  int x, y;
+};
+__device__ __forceinline__ Pix pix_of(int p, int nx) {
+  const int y = p / nx;
+  return {p - y * nx, y};
+}
+// neighbour of q for tap = 3 ky + kx: (x + kx - 1, y + ky - 1), periodic
+__device__ __forceinline__ int nbr(Pix q, int tap, int nx, int ny) {
+  const int ky = tap / 3, kx = tap - 3 * ky;
+  int yy = q.y + ky - 1, xx = q.x + kx - 1;
   yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
   xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
   return yy * nx + xx;
@@ -54,54 +62,71 @@ constexpr int kp_of(int cin) { return (9 * cin + 15) / 16 * 16; }
 
 // ---------------------------------------------------------------- forward --
 // Z[p][co] = b[co] + sum_k Wt[co][k] X[p + off(tap)][ci];  A = bf16(relu(Z)).
-// One wave computes 16 pixels x all output channels.
-template <int CIN, int COUT>
+// The bf16 weight matrix is staged in LDS once per workgroup (rows padded by 4
+// so that the 16 rows a fragment reads fall in different banks).  A wave
+// computes FWD_MT tiles of 16 pixels x all output channels; for each tile all
+// activation loads are issued before its MFMAs (FWD_MT at most; fewer on small
+// lattices so that the grid still fills the chip).  STORE_Z keeps the FP32
+// pre-activation (the ReLU mask of the backward pass); STORE_A writes the bf16
+// activation (the next layer's input).
+constexpr int FWD_MT = 4;
+template <int CIN, int COUT, bool RELU, bool STORE_Z, bool STORE_A>
 __global__ void __launch_bounds__(256) conv_fwd(const bf16* __restrict__ X, const bf16* __restrict__ Wt,
                                                 const float* __restrict__ bias, float* __restrict__ Z,
-                                                bf16* __restrict__ A, int nx, int ny, int relu) {
-  constexpr int K = 9 * CIN, KP = kp_of(CIN), NT = (COUT + 15) / 16;
+                                                bf16* __restrict__ A, int nx, int ny, int mtw) {
+  constexpr int K = 9 * CIN, KP = kp_of(CIN), KS = KP / 16, NT = (COUT + 15) / 16, ROWS = 16 * NT;
+  constexpr int KL = KP + 4;  // LDS row stride (elements)
+  __shared__ __attribute__((aligned(16))) bf16 wl[ROWS * KL];
+  for (int e = threadIdx.x; e < ROWS * (KP / 4); e += 256) {
+    const int r = e / (KP / 4), c = e - r * (KP / 4);
+    *reinterpret_cast<bf16x4*>(wl + r * KL + 4 * c) = *reinterpret_cast<const bf16x4*>(Wt + (size_t)r * KP + 4 * c);
+  }
+  __syncthreads();
   const int P = nx * ny;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int p0 = (blockIdx.x * 4 + wave) * 16;
-  if (p0 >= P) return;
   const int i = lane & 15, g = lane >> 4;
-  const int pa = min(p0 + i, P - 1);  // A-operand row (pixel)
-  f32x4 acc[NT];
+  for (int m = 0; m < mtw; ++m) {
+    const int p0 = ((blockIdx.x * 4 + wave) * mtw + m) * 16;
+    if (p0 >= P) break;  // wave-uniform; no barrier follows
+    const Pix qa = pix_of(min(p0 + i, P - 1), nx);  // A-operand row (pixel)
+    bf16x4 a[KS];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int ks = 0; ks < KP / 16; ++ks) {
-    bf16x4 a;
-    const int k0 = ks * 16 + 4 * g;  // 4 consecutive k share a tap (CIN % 4 == 0)
-    if (k0 < K) {
-      const int tap = k0 / CIN, ci = k0 - tap * CIN;
-      const bf16* src = X + (size_t)tap_pixel(pa, tap, nx, ny) * CIN + ci;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) a[v] = (short)src[v];
-    } else {
-      a = bf16x4{0, 0, 0, 0};
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k0 = ks * 16 + 4 * g;  // 4 consecutive k share a tap (CIN % 4 == 0)
+      if (k0 < K) {
+        const int tap = k0 / CIN, ci = k0 - tap * CIN;
+        // 8-byte load: CIN and ci are multiples of 4, the buffers 256-aligned
+        a[ks] = *reinterpret_cast<const bf16x4*>(X + (size_t)nbr(qa, tap, nx, ny) * CIN + ci);
+      } else {
+        a[ks] = bf16x4{0, 0, 0, 0};
+      }
     }
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k0 = ks * 16 + 4 * g;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bf16x4 b = *reinterpret_cast<const bf16x4*>(wl + (t * 16 + i) * KL + k0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], b, acc[t], 0, 0, 0);
+      }
+    }
+    // lane holds D[4g + v][i]: pixel p0 + 4g + v, channel t * 16 + i
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      bf16x4 b;
-      const bf16* w = Wt + (size_t)(t * 16 + i) * KP + k0;
+      const int co = t * 16 + i;
+      if (co >= COUT) continue;
+      const float bc = bias[co];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) b[v] = (short)w[v];
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-    }
-  }
-  // lane holds D[4g + v][i]: pixel p0 + 4g + v, channel t * 16 + i
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = t * 16 + i;
-    if (co >= COUT) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int p = p0 + 4 * g + v;
-      if (p >= P) continue;
-      const float z = acc[t][v] + bias[co];
-      Z[(size_t)p * COUT + co] = z;
-      A[(size_t)p * COUT + co] = to_bf16(relu ? fmaxf(z, 0.f) : z);
+      for (int v = 0; v < 4; ++v) {
+        const int p = p0 + 4 * g + v;
+        if (p >= P) continue;
+        const float z = acc[t][v] + bc;
+        if (STORE_Z) Z[(size_t)p * COUT + co] = z;
+        if (STORE_A) A[(size_t)p * COUT + co] = to_bf16(RELU ? fmaxf(z, 0.f) : z);
+      }
     }
   }
 }
@@ -121,7 +146,7 @@ __global__ void __launch_bounds__(256) conv_bwd_data(const bf16* __restrict__ G,
   const int q0 = (blockIdx.x * 4 + wave) * 16;
   if (q0 >= P) return;
   const int i = lane & 15, g = lane >> 4;
-  const int qa = min(q0 + i, P - 1);
+  const Pix qa = pix_of(min(q0 + i, P - 1), nx);
   f32x4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -131,10 +156,8 @@ __global__ void __launch_bounds__(256) conv_bwd_data(const bf16* __restrict__ G,
     bf16x4 a;
     if (k0 < K) {
       const int tap = k0 / COUT, co = k0 - tap * COUT;
-      // neighbour q - off(tap): the tap mirrored through the centre
-      const bf16* src = G + (size_t)tap_pixel(qa, 8 - tap, nx, ny) * COUT + co;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) a[v] = (short)src[v];
+      // neighbour q - off(tap): the tap mirrored through the centre (8-byte load)
+      a = *reinterpret_cast<const bf16x4*>(G + (size_t)nbr(qa, 8 - tap, nx, ny) * COUT + co);
     } else {
       a = bf16x4{0, 0, 0, 0};
     }
@@ -171,77 +194,83 @@ __global__ void __launch_bounds__(256) conv_bwd_data(const bf16* __restrict__ G,
 
 // --------------------------------------------------------- backward weight --
 // dW[co][ci][tap] += sum_p G[p][co] X[p + off(tap)][ci]  (GEMM M = COUT,
-// N = 9 CIN, reduction over a chunk of pixels per workgroup; the output
-// tiles are shared out among the 4 waves; FP32 atomics add the partial sums).
+// N = 9 CIN, reduction over pixels).  Each wave owns one 16 x 16 output tile
+// (blockIdx.x picks 4 tiles) and reduces it over one pixel chunk
+// (blockIdx.y); FP32 atomics add the chunks' partial sums.
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) conv_bwd_weight(const bf16* __restrict__ G, const bf16* __restrict__ X,
                                                        float* __restrict__ dW, int nx, int ny, int chunk) {
   constexpr int K = 9 * CIN, KP = kp_of(CIN), MT = (COUT + 15) / 16, NTK = KP / 16;
-  constexpr int TILES = MT * NTK, PER = (TILES + 3) / 4;
+  constexpr int TILES = MT * NTK;
   const int P = nx * ny;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tile = blockIdx.x * 4 + wave;
+  if (tile >= TILES) return;
   const int i = lane & 15, g = lane >> 4;
-  const int pbeg = blockIdx.x * chunk, pend = min(pbeg + chunk, P);
-  f32x4 acc[PER];
+  const int mt = tile / NTK, nt = tile - mt * NTK;
+  const int co = mt * 16 + i;             // A-operand row: output channel
+  const int k = nt * 16 + i;              // B-operand column: tap * CIN + ci
+  const int tap = k / CIN, ci = k - tap * CIN;
+  const bool co_ok = co < COUT, k_ok = k < K;
+  const int pbeg = blockIdx.y * chunk, pend = min(pbeg + chunk, P);
+  // two accumulators over alternate 16-pixel steps keep more loads in flight
+  f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+  // coordinates of this lane's 4 pixels in the current and the next step
+  Pix q[2][4];
 #pragma unroll
-  for (int s = 0; s < PER; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int p0 = pbeg; p0 < pend; p0 += 16) {
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int tile = wave * PER + s;
-      if (tile >= TILES) continue;
-      const int mt = tile / NTK, nt = tile - mt * NTK;
-      bf16x4 a, b;
-      const int co = mt * 16 + i;
-      const int k = nt * 16 + i;
-      const int tap = k / CIN, ci = k - tap * CIN;
+    for (int v = 0; v < 4; ++v) q[h][v] = pix_of(min(pbeg + 16 * h + 4 * g + v, P - 1), nx);
+  for (int p0 = pbeg; p0 < pend; p0 += 32) {
+    bf16x4 a[2], b[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int p = p0 + 4 * g + v;
+        const int p = p0 + 16 * h + 4 * g + v;
         const bool ok = p < pend;
-        a[v] = (ok && co < COUT) ? (short)G[(size_t)p * COUT + co] : (short)0;
-        b[v] = (ok && k < K) ? (short)X[(size_t)tap_pixel(p, tap, nx, ny) * CIN + ci] : (short)0;
+        a[h][v] = (ok && co_ok) ? (short)G[(size_t)p * COUT + co] : (short)0;
+        b[h][v] = (ok && k_ok) ? (short)X[(size_t)nbr(q[h][v], tap, nx, ny) * CIN + ci] : (short)0;
       }
-      acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[s], 0, 0, 0);
-    }
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[0], acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[1], acc1, 0, 0, 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        q[h][v].x += 32;
+        while (q[h][v].x >= nx) {  // at most ceil(32 / nx) passes
+          q[h][v].x -= nx;
+          ++q[h][v].y;
+        }
+      }
   }
+  const f32x4 acc = acc0 + acc1;
   // lane holds D[4g + v][i]: output channel mt*16 + 4g + v, k = nt*16 + i
+  if (!k_ok) return;
 #pragma unroll
-  for (int s = 0; s < PER; ++s) {
-    const int tile = wave * PER + s;
-    if (tile >= TILES) continue;
-    const int mt = tile / NTK, nt = tile - mt * NTK;
-    const int k = nt * 16 + i;
-    if (k >= K) continue;
-    const int tap = k / CIN, ci = k - tap * CIN;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int co = mt * 16 + 4 * g + v;
-      if (co < COUT) atomicAdd(&dW[((size_t)co * CIN + ci) * 9 + tap], acc[s][v]);
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int c = mt * 16 + 4 * g + v;
+    if (c < COUT) atomicAdd(&dW[((size_t)c * CIN + ci) * 9 + tap], acc[v]);
   }
 }
 
-// db[c] += sum_p G[p][c]
+// db[c] += sum_p G[p][c]: thread (row r, channel c) of a block sums channel c
+// over rows r, r + R, ... (coalesced rows of C values), then one LDS reduction
 template <int C>
 __global__ void __launch_bounds__(256) bias_grad(const bf16* __restrict__ G, float* __restrict__ db, int P) {
+  constexpr int R = 256 / C;
   __shared__ float part[256];
-  float s[C];
+  const int c = threadIdx.x % C, r = threadIdx.x / C;
+  float s = 0.f;
+  for (int p = blockIdx.x * R + r; p < P; p += gridDim.x * R) s += from_bf16(G[(size_t)p * C + c]);
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < C) {
+    float t = 0.f;
 #pragma unroll
-  for (int c = 0; c < C; ++c) s[c] = 0.f;
-  for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256)
-#pragma unroll
-    for (int c = 0; c < C; ++c) s[c] += from_bf16(G[(size_t)p * C + c]);
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    part[threadIdx.x] = s[c];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(&db[c], part[0]);
-    __syncthreads();
+    for (int j = 0; j < R; ++j) t += part[j * C + threadIdx.x];
+    atomicAdd(&db[threadIdx.x], t);
   }
 }
 
@@ -495,18 +524,35 @@ struct olb_closure {
   }
 
   int pix_blocks() const { return (P + 63) / 64; }  // 4 waves x 16 pixels
+  // 16-pixel tiles per wave of the forward convolutions: up to FWD_MT while
+  // at least 1024 workgroups remain
+  int fwd_mtw() const { return std::max(1, std::min(olbk::FWD_MT, P / (64 * 1024))); }
+  int fwd_blocks() const { return (P + 64 * fwd_mtw() - 1) / (64 * fwd_mtw()); }
 
-  olb_status forward(const double* dev_m) {
+  // keep_z: also store the pre-activations of the hidden layers (backward)
+  olb_status forward(const double* dev_m, bool keep_z) {
     using namespace olbk;
+    const float* par = at<float>(L.par);
+    const float* b1 = par + 32 * 4 * 9;
+    const float* b2 = par + (32 * 4 * 9 + 32) + 32 * 32 * 9;
+    const float* b3 = par + (NPARAM - 4);
     hipLaunchKernelGGL(prep_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, dev_m, P, norm, at<bf16>(L.x0));
-    hipLaunchKernelGGL((conv_fwd<4, 32>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.x0),
-                       at<bf16>(L.w1), at<float>(L.par) + 32 * 4 * 9, at<float>(L.z1), at<bf16>(L.a1), nx, ny, 1);
-    hipLaunchKernelGGL((conv_fwd<32, 32>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.a1),
-                       at<bf16>(L.w2), at<float>(L.par) + (32 * 4 * 9 + 32) + 32 * 32 * 9, at<float>(L.z2),
-                       at<bf16>(L.a2), nx, ny, 1);
-    // layer 3: no activation; its bf16 copy goes to the (unused) g3 slot first
-    hipLaunchKernelGGL((conv_fwd<32, 4>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.a2),
-                       at<bf16>(L.w3), at<float>(L.par) + (NPARAM - 4), at<float>(L.z3), at<bf16>(L.g3), nx, ny, 0);
+    const dim3 fg(fwd_blocks());
+    const int mtw = fwd_mtw();
+    if (keep_z) {
+      hipLaunchKernelGGL((conv_fwd<4, 32, true, true, true>), fg, dim3(256), 0, stream,
+                         at<bf16>(L.x0), at<bf16>(L.w1), b1, at<float>(L.z1), at<bf16>(L.a1), nx, ny, mtw);
+      hipLaunchKernelGGL((conv_fwd<32, 32, true, true, true>), fg, dim3(256), 0, stream,
+                         at<bf16>(L.a1), at<bf16>(L.w2), b2, at<float>(L.z2), at<bf16>(L.a2), nx, ny, mtw);
+    } else {
+      hipLaunchKernelGGL((conv_fwd<4, 32, true, false, true>), fg, dim3(256), 0, stream,
+                         at<bf16>(L.x0), at<bf16>(L.w1), b1, at<float>(L.z1), at<bf16>(L.a1), nx, ny, mtw);
+      hipLaunchKernelGGL((conv_fwd<32, 32, true, false, true>), fg, dim3(256), 0, stream,
+                         at<bf16>(L.a1), at<bf16>(L.w2), b2, at<float>(L.z2), at<bf16>(L.a2), nx, ny, mtw);
+    }
+    // layer 3: no activation, only the FP32 output
+    hipLaunchKernelGGL((conv_fwd<32, 4, false, true, false>), fg, dim3(256), 0, stream,
+                       at<bf16>(L.a2), at<bf16>(L.w3), b3, at<float>(L.z3), at<bf16>(L.g3), nx, ny, mtw);
     return hip(hipGetLastError(), "closure forward");
   }
 
@@ -520,25 +566,36 @@ struct olb_closure {
     hipLaunchKernelGGL(loss_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, at<float>(L.z3), dev_m, dev_ref,
                        P, norm, at<bf16>(L.g3), at<float>(L.loss));
     const int O2 = 32 * 4 * 9 + 32, O3 = O2 + 32 * 32 * 9 + 32;
-    const int chunk = 1024;
-    const int wb = (P + chunk - 1) / chunk;
+    const int bias_blocks = std::min(1024, std::max(1, P / 256));
     // layer 3
-    hipLaunchKernelGGL((conv_bwd_weight<32, 4>), dim3(wb), dim3(256), 0, stream, at<bf16>(L.g3), at<bf16>(L.a2),
-                       grad + O3, nx, ny, chunk);
-    hipLaunchKernelGGL((bias_grad<4>), dim3(256), dim3(256), 0, stream, at<bf16>(L.g3), grad + O3 + 4 * 32 * 9, P);
+    launch_bwd_weight<32, 4>(at<bf16>(L.g3), at<bf16>(L.a2), grad + O3);
+    hipLaunchKernelGGL((bias_grad<4>), dim3(bias_blocks), dim3(256), 0, stream, at<bf16>(L.g3),
+                       grad + O3 + 4 * 32 * 9, P);
     hipLaunchKernelGGL((conv_bwd_data<32, 4>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.g3),
                        at<bf16>(L.w3), at<float>(L.z2), at<bf16>(L.g2), nx, ny);
     // layer 2
-    hipLaunchKernelGGL((conv_bwd_weight<32, 32>), dim3(wb), dim3(256), 0, stream, at<bf16>(L.g2),
-                       at<bf16>(L.a1), grad + O2, nx, ny, chunk);
-    hipLaunchKernelGGL((bias_grad<32>), dim3(256), dim3(256), 0, stream, at<bf16>(L.g2), grad + O2 + 32 * 32 * 9, P);
+    launch_bwd_weight<32, 32>(at<bf16>(L.g2), at<bf16>(L.a1), grad + O2);
+    hipLaunchKernelGGL((bias_grad<32>), dim3(bias_blocks), dim3(256), 0, stream, at<bf16>(L.g2),
+                       grad + O2 + 32 * 32 * 9, P);
     hipLaunchKernelGGL((conv_bwd_data<32, 32>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.g2),
                        at<bf16>(L.w2), at<float>(L.z1), at<bf16>(L.g1), nx, ny);
     // layer 1 (the input needs no gradient)
-    hipLaunchKernelGGL((conv_bwd_weight<4, 32>), dim3(wb), dim3(256), 0, stream, at<bf16>(L.g1), at<bf16>(L.x0),
-                       grad, nx, ny, chunk);
-    hipLaunchKernelGGL((bias_grad<32>), dim3(256), dim3(256), 0, stream, at<bf16>(L.g1), grad + 32 * 4 * 9, P);
+    launch_bwd_weight<4, 32>(at<bf16>(L.g1), at<bf16>(L.x0), grad);
+    hipLaunchKernelGGL((bias_grad<32>), dim3(bias_blocks), dim3(256), 0, stream, at<bf16>(L.g1),
+                       grad + 32 * 4 * 9, P);
     return hip(hipGetLastError(), "closure backward");
+  }
+
+  // about 512 workgroups per weight gradient: tile groups x pixel chunks
+  template <int CIN, int COUT>
+  void launch_bwd_weight(const olbk::bf16* G, const olbk::bf16* X, float* dW) {
+    constexpr int tiles = ((COUT + 15) / 16) * (olbk::kp_of(CIN) / 16);
+    constexpr int groups = (tiles + 3) / 4;
+    const int chunks = std::max(1, std::min((P + 63) / 64, 512 / groups));
+    const int chunk = ((P + chunks - 1) / chunks + 15) / 16 * 16;
+    const int nchunks = (P + chunk - 1) / chunk;
+    hipLaunchKernelGGL((olbk::conv_bwd_weight<CIN, COUT>), dim3(groups, nchunks), dim3(256), 0, stream, G, X, dW,
+                       nx, ny, chunk);
   }
 
   olb_status pack() {
@@ -631,7 +688,7 @@ olb_status olb_closure_get_params(olb_closure* c, float* params) {
 olb_status olb_closure_forward(olb_closure* c, const double* dev_moments, double* dev_delta) {
   if (!c || !dev_moments || !dev_delta) return OLB_E_ARG;
   if (!c->have_params) return OLB_E_STATE;
-  olb_status s = c->forward(dev_moments);
+  olb_status s = c->forward(dev_moments, false);
   if (s) return s;
   double* sums = c->at<double>(c->L.sums);
   if (c->conserve_mask) {
@@ -656,7 +713,7 @@ olb_status olb_closure_gradients(olb_closure* c, const double* dev_moments, cons
                                  float* grad, float* loss) {
   if (!c || !dev_moments || !dev_reference || !grad) return OLB_E_ARG;
   if (!c->have_params) return OLB_E_STATE;
-  olb_status s = c->forward(dev_moments);
+  olb_status s = c->forward(dev_moments, true);
   if (!s) s = c->backward(dev_moments, dev_reference);
   if (!s) s = c->hip(hipMemcpyAsync(grad, c->at<float>(c->L.grad), NPARAM * 4, hipMemcpyDeviceToHost,
                                     c->stream), "grad download");
@@ -670,7 +727,7 @@ olb_status olb_closure_train_step(olb_closure* c, const double* dev_moments, con
                                   float lr, float* loss) {
   if (!c || !dev_moments || !dev_reference || !(lr > 0.f)) return OLB_E_ARG;
   if (!c->have_params) return OLB_E_STATE;
-  olb_status s = c->forward(dev_moments);
+  olb_status s = c->forward(dev_moments, true);
   if (!s) s = c->backward(dev_moments, dev_reference);
   if (s) return s;
   c->adam_t += 1;

@@ -229,6 +229,10 @@ olb_status olb_closure_get_params(olb_closure* c, float* params);
  * [4][ny][nx] (double), scaled by out_scale and projected as set by
  * olb_closure_set_conserve.  Asynchronous.  OLB_E_STATE before set_params. */
 olb_status olb_closure_forward(olb_closure* c, const double* dev_moments, double* dev_delta);
+/* The same through the training path's kernels (one launch per layer, the
+ * activations in the workspace) instead of the fused one-tile-per-workgroup
+ * kernel; without projection (mask 0) the two agree to the bit. */
+olb_status olb_closure_forward_layers(olb_closure* c, const double* dev_moments, double* dev_delta);
 /* Conservative projection of forward / apply: bit c of mask (c = 0 n,
  * 1 u_x, 2 u_y, 3 T) removes the lattice mean of that correction channel, so
  * that, e.g., the total mass is unchanged by apply (bit 0).  Default 7 (n,

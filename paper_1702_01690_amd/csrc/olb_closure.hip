@@ -419,6 +419,165 @@ __global__ void delta_kernel(const float* __restrict__ Z3, int P, Norm nm, const
   }
 }
 
+// ------------------------------------------------------- fused inference --
+// The whole network for one 16 x 16 output tile in one workgroup of 8 waves:
+// the normalised input on the 22 x 22 region around the tile, layer 1 on
+// 20 x 20, layer 2 on 18 x 18 and layer 3 on the tile itself, every
+// intermediate in LDS (the halo rows are recomputed by neighbouring tiles).
+// Same operands, instruction and k order as the layer-by-layer kernels, so
+// the network output is the same to the bit; only the moment planes and the
+// corrections touch HBM.  Channel sums of the output (for the conservative
+// projection) are added to sums[4] when sums != nullptr.
+constexpr int FT = 16;            // output tile edge
+constexpr int R0 = FT + 6, R1 = FT + 4, R2 = FT + 2;
+// the current layer's weight matrix, rows padded by 4 (bank spread)
+constexpr int WL = kp_of(32) + 4;
+// hidden activations: 32 channels per pixel padded to 36, so that the 16
+// pixels one fragment reads start in 16 different bank pairs
+constexpr int HS = 36;
+struct InferLds {
+  bf16 x0[R0 * R0 * 4];
+  bf16 a1[R1 * R1 * HS];
+  bf16 a2[R2 * R2 * HS];
+  bf16 w[32 * WL];
+  double part[8][4];
+};
+
+// copy a bf16 weight matrix (rows x KP) into LDS with row stride KP + 4
+template <int ROWS, int KP>
+__device__ __forceinline__ void stage_weights(bf16* w, const bf16* __restrict__ Wt, int tid) {
+  for (int e = tid; e < ROWS * (KP / 4); e += 512) {
+    const int r = e / (KP / 4), c = e - r * (KP / 4);
+    *reinterpret_cast<bf16x4*>(w + r * (KP + 4) + 4 * c) = *reinterpret_cast<const bf16x4*>(Wt + (size_t)r * KP + 4 * c);
+  }
+}
+
+// MFMA layer on an R x R output region from an (R + 2) x (R + 2) input
+// region in LDS: m-tiles of 16 region pixels (row-major), spread over the
+// 8 waves.  Returns nothing; the epilogue functor gets (pixel, channel, z).
+template <int CIN, int COUT, int R, int IS, typename Epi>
+__device__ __forceinline__ void lds_layer(const bf16* in, const bf16* w, const float* __restrict__ bias,
+                                          int wave, int lane, Epi epi) {
+  constexpr int K = 9 * CIN, KP = kp_of(CIN), KS = KP / 16, NT = (COUT + 15) / 16;
+  constexpr int NPIX = R * R, MTILES = (NPIX + 15) / 16, RI = R + 2;
+  const int i = lane & 15, g = lane >> 4;
+  for (int mt = wave; mt < MTILES; mt += 8) {
+    const int j = min(mt * 16 + i, NPIX - 1);   // A-operand row: region pixel
+    const int r = j / R, c = j - r * R;
+    bf16x4 a[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k0 = ks * 16 + 4 * g;
+      if (k0 < K) {
+        const int tap = k0 / CIN, ci = k0 - tap * CIN;
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        a[ks] = *reinterpret_cast<const bf16x4*>(in + ((r + ky) * RI + c + kx) * IS + ci);
+      } else {
+        a[ks] = bf16x4{0, 0, 0, 0};
+      }
+    }
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k0 = ks * 16 + 4 * g;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bf16x4 b = *reinterpret_cast<const bf16x4*>(w + (t * 16 + i) * (KP + 4) + k0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], b, acc[t], 0, 0, 0);
+      }
+    }
+    // lane holds D[4g + v][i]: region pixel mt*16 + 4g + v, channel t*16 + i
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + i;
+      if (co >= COUT) continue;
+      const float bc = bias[co];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int q = mt * 16 + 4 * g + v;
+        if (q < NPIX) epi(q, co, acc[t][v] + bc);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(512) infer_kernel(const double* __restrict__ m, Norm nm,
+                                                    const bf16* __restrict__ W1, const bf16* __restrict__ W2,
+                                                    const bf16* __restrict__ W3, const float* __restrict__ b1,
+                                                    const float* __restrict__ b2, const float* __restrict__ b3,
+                                                    int nx, int ny, int tiles_x, double* __restrict__ delta,
+                                                    double* __restrict__ sums) {
+  __shared__ InferLds sm;
+  const int P = nx * ny;
+  const int ty0 = (blockIdx.x / tiles_x) * FT, tx0 = (blockIdx.x % tiles_x) * FT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // normalised input on the 22 x 22 region (periodic wrap)
+  for (int e = tid; e < R0 * R0; e += 512) {
+    const int r = e / R0, c = e - r * R0;
+    int gy = (ty0 - 3 + r) % ny, gx = (tx0 - 3 + c) % nx;
+    gy += gy < 0 ? ny : 0;
+    gx += gx < 0 ? nx : 0;
+    const size_t p = (size_t)gy * nx + gx;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+      sm.x0[e * 4 + ch] = to_bf16((float)((m[(size_t)ch * P + p] - nm.in_mean[ch]) * nm.in_inv_scale[ch]));
+  }
+  stage_weights<32, kp_of(4)>(sm.w, W1, tid);
+  __syncthreads();
+  lds_layer<4, 32, R1, 4>(sm.x0, sm.w, b1, wave, lane,
+                          [&](int q, int co, float z) { sm.a1[q * HS + co] = to_bf16(fmaxf(z, 0.f)); });
+  __syncthreads();
+  stage_weights<32, kp_of(32)>(sm.w, W2, tid);
+  __syncthreads();
+  lds_layer<32, 32, R2, HS>(sm.a1, sm.w, b2, wave, lane,
+                            [&](int q, int co, float z) { sm.a2[q * HS + co] = to_bf16(fmaxf(z, 0.f)); });
+  __syncthreads();
+  stage_weights<16, kp_of(32)>(sm.w, W3, tid);
+  __syncthreads();
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  lds_layer<32, 4, FT, HS>(sm.a2, sm.w, b3, wave, lane, [&](int q, int co, float z) {
+    const int r = q / FT, c = q - r * FT;
+    const int gy = ty0 + r, gx = tx0 + c;
+    if (gy < ny && gx < nx) {
+      delta[(size_t)co * P + (size_t)gy * nx + gx] = (double)z * (double)nm.out_scale[co];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k == co) s[k] += (double)z;
+    }
+  });
+  if (sums) {
+    // lanes hold channel (lane & 15): fold the four lane groups, then waves
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double v = s[k];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      s[k] = v;
+    }
+    if (lane < 4) sm.part[wave][lane] = s[lane];
+    __syncthreads();
+    if (tid < 4) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) t += sm.part[w][tid];
+      atomicAdd(&sums[tid], t);
+    }
+  }
+}
+
+// delta[c] -= mean_c * out_scale[c] for the channels in mask (sums: channel
+// totals of the normalised output over P nodes)
+__global__ void project_kernel(double* __restrict__ delta, int P, Norm nm, const double* __restrict__ sums,
+                               int mask) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if ((mask >> c) & 1) delta[(size_t)c * P + p] -= sums[c] / (double)P * (double)nm.out_scale[c];
+}
+
 // f <- f + f^eq(m') - f^eq(m) with m' = m + dm (absolute == 0) or m' = dm
 // (absolute == 1) where m' is admissible (finite, 0 < n < 1/b, T > 0); other
 // nodes keep f (counted in skipped).
@@ -556,6 +715,42 @@ struct olb_closure {
     return hip(hipGetLastError(), "closure forward");
   }
 
+  // corrections for device moments through the fused kernel, projected
+  olb_status infer(const double* dev_m, double* dev_delta) {
+    using namespace olbk;
+    const float* par = at<float>(L.par);
+    double* sums = conserve_mask ? at<double>(L.sums) : nullptr;
+    if (sums) {
+      olb_status s = hip(hipMemsetAsync(sums, 0, 4 * sizeof(double), stream), "sums clear");
+      if (s) return s;
+    }
+    const int tiles_x = (nx + FT - 1) / FT, tiles_y = (ny + FT - 1) / FT;
+    hipLaunchKernelGGL(infer_kernel, dim3(tiles_x * tiles_y), dim3(512), 0, stream, dev_m, norm, at<bf16>(L.w1),
+                       at<bf16>(L.w2), at<bf16>(L.w3), par + 32 * 4 * 9, par + (32 * 4 * 9 + 32) + 32 * 32 * 9,
+                       par + (NPARAM - 4), nx, ny, tiles_x, dev_delta, sums);
+    if (sums)
+      hipLaunchKernelGGL(project_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, dev_delta, P, norm, sums,
+                         conserve_mask);
+    return hip(hipGetLastError(), "closure inference");
+  }
+
+  // layer-by-layer forward (the reference for the fused kernel; training)
+  olb_status forward_layers(const double* dev_m, double* dev_delta) {
+    using namespace olbk;
+    olb_status s = forward(dev_m, false);
+    if (s) return s;
+    double* sums = at<double>(L.sums);
+    if (conserve_mask) {
+      s = hip(hipMemsetAsync(sums, 0, 4 * sizeof(double), stream), "sums clear");
+      if (s) return s;
+      const int blocks = std::min(1024, (P + 255) / 256);
+      hipLaunchKernelGGL(output_sums, dim3(blocks), dim3(256), 0, stream, at<float>(L.z3), P, sums);
+    }
+    hipLaunchKernelGGL(delta_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, at<float>(L.z3), P, norm, sums,
+                       conserve_mask, dev_delta);
+    return hip(hipGetLastError(), "delta kernel");
+  }
+
   olb_status backward(const double* dev_m, const double* dev_ref) {
     using namespace olbk;
     float* grad = at<float>(L.grad);
@@ -688,21 +883,14 @@ olb_status olb_closure_get_params(olb_closure* c, float* params) {
 olb_status olb_closure_forward(olb_closure* c, const double* dev_moments, double* dev_delta) {
   if (!c || !dev_moments || !dev_delta) return OLB_E_ARG;
   if (!c->have_params) return OLB_E_STATE;
-  olb_status s = c->forward(dev_moments, false);
-  if (s) return s;
-  double* sums = c->at<double>(c->L.sums);
-  if (c->conserve_mask) {
-    s = c->hip(hipMemsetAsync(sums, 0, 4 * sizeof(double), c->stream), "sums clear");
-    if (s) return s;
-    const int blocks = std::min(1024, (c->P + 255) / 256);
-    hipLaunchKernelGGL(olbk::output_sums, dim3(blocks), dim3(256), 0, c->stream, c->at<float>(c->L.z3), c->P,
-                       sums);
-  }
-  hipLaunchKernelGGL(olbk::delta_kernel, dim3((c->P + 255) / 256), dim3(256), 0, c->stream,
-                     c->at<float>(c->L.z3), c->P, c->norm, sums, c->conserve_mask, dev_delta);
-  return c->hip(hipGetLastError(), "delta kernel");
+  return c->infer(dev_moments, dev_delta);
 }
 
+olb_status olb_closure_forward_layers(olb_closure* c, const double* dev_moments, double* dev_delta) {
+  if (!c || !dev_moments || !dev_delta) return OLB_E_ARG;
+  if (!c->have_params) return OLB_E_STATE;
+  return c->forward_layers(dev_moments, dev_delta);
+}
 olb_status olb_closure_set_conserve(olb_closure* c, int32_t mask) {
   if (!c || mask < 0 || mask > 15) return OLB_E_ARG;
   c->conserve_mask = mask;

@@ -94,6 +94,7 @@ _SIGS = {
     "olb_closure_set_params": ([_vp, _fp], ctypes.c_int),
     "olb_closure_get_params": ([_vp, _fp], ctypes.c_int),
     "olb_closure_forward": ([_vp, _vp, _vp], ctypes.c_int),
+    "olb_closure_forward_layers": ([_vp, _vp, _vp], ctypes.c_int),
     "olb_closure_gradients": ([_vp, _vp, _vp, _fp, _fp], ctypes.c_int),
     "olb_closure_train_step": ([_vp, _vp, _vp, ctypes.c_float, _fp], ctypes.c_int),
     "olb_closure_apply": ([_vp, _vp, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -530,6 +531,10 @@ def olb_closure_forward(h, dev_moments, dev_delta):
     _check(lib().olb_closure_forward(h, _vp(dev_moments), _vp(dev_delta)), h, "closure")
 
 
+def olb_closure_forward_layers(h, dev_moments, dev_delta):
+    _check(lib().olb_closure_forward_layers(h, _vp(dev_moments), _vp(dev_delta)), h, "closure")
+
+
 def olb_closure_gradients(h, dev_moments, dev_reference):
     g = np.empty(NPARAM, dtype=np.float32)
     loss = np.zeros(1, dtype=np.float32)
@@ -631,6 +636,9 @@ class Closure:
 
     def forward(self, moments, delta):
         olb_closure_forward(self.h, self._planes(moments), self._planes(delta))
+
+    def forward_layers(self, moments, delta):
+        olb_closure_forward_layers(self.h, self._planes(moments), self._planes(delta))
 
     def gradients(self, moments, reference):
         return olb_closure_gradients(self.h, self._planes(moments), self._planes(reference))

@@ -100,6 +100,31 @@ def test_forward_matches_oracle(shape, mask):
     assert e_x < 3e-2
 
 
+@pytest.mark.parametrize("shape", [(37, 23), (64, 48), (16, 16), (5, 3), (130, 17)])
+def test_fused_inference_equals_layer_by_layer_forward(shape):
+    """The one-tile-per-workgroup kernel (ragged edge tiles, lattices smaller
+    than its halo) against the training path's per-layer kernels."""
+    torch, olb = _env()
+    nx, ny = shape
+    params, m, _, norm = _setup(nx, ny, seed=17)
+    c = olb.Closure(nx, ny)
+    c.set_norm(*norm)
+    c.set_params(params)
+    dm = _dev(torch, m)
+    fused, layers = torch.empty_like(dm), torch.empty_like(dm)
+    c.set_conserve(0)
+    c.forward(dm, fused)
+    c.forward_layers(dm, layers)
+    torch.cuda.synchronize()
+    assert torch.equal(fused, layers)
+    c.set_conserve(7)
+    c.forward(dm, fused)
+    c.forward_layers(dm, layers)
+    torch.cuda.synchronize()
+    f, l = fused.cpu().numpy(), layers.cpu().numpy()
+    assert np.abs(f - l).max() <= 1e-12 * np.abs(l).max()
+
+
 @pytest.mark.parametrize("shape", [(37, 23), (64, 64)])
 def test_gradients_match_oracle(shape):
     torch, olb = _env()

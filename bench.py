@@ -223,7 +223,8 @@ def run_closure(args):
                        "free_run_end_max": [roll_p[-1][0], roll_f[-1][0]],
                        "free_run_end_rms": [roll_p[-1][1], roll_f[-1][1]],
                        "order": "[plain coarse, coarse + closure]", "skipped_nodes": skipped}},
-        "roofline": {"bound": "mfma", "kernel": "network forward (3 bf16 implicit-GEMM convolutions)",
+        "roofline": {"bound": "mfma", "kernel": "network forward (fused: one 16x16 tile per workgroup, "
+                               "three bf16 implicit-GEMM convolutions in LDS, plus the projection)",
                      "achieved": round(fwd_tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(fwd_tflops / MFMA_BF16_PEAK_TFLOPS, 5), "traffic": None,
                      "forward_ms": round(fwd_s * 1e3, 4)},

@@ -233,6 +233,26 @@ def run_closure(args):
     print(json.dumps(out))
 
 
+class _Sequential:
+    """Single-instance lattices stepped one after another (same stream)."""
+
+    def __init__(self, lats):
+        self.lats = lats
+        self.stream = lats[0].stream
+
+    def step(self, n):
+        for one in self.lats:
+            one.step(n)
+
+    def sync(self):
+        for one in self.lats:
+            one.sync()
+
+    def close(self):
+        for one in self.lats:
+            one.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +265,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2000,
                     help="oracle steps of the CPU-baseline sample (about 10-20 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "fp32"],
+                    help="override the workload's storage precision (speedup comparisons)")
+    ap.add_argument("--sequential", action="store_true",
+                    help="batched workload: step the instances as separate lattices, one after another")
     ap.add_argument("--closure-samples", type=int, default=64,
                     help="training trajectories of the closure workload (8 pairs each)")
     ap.add_argument("--closure-epochs", type=int, default=30)
@@ -267,12 +291,28 @@ def main():
     from paper_1702_01690_amd import olb
 
     cases = make_cases(args.workload)
+    if args.precision != "auto":
+        import olb_inputs as I
+        for c in cases:
+            c.params["precision"] = 0 if args.precision == "fp64" else 1
+            c.params["rho_ref"] = I.N_CRIT if args.workload != "wave2048" else 1.0
     precision = cases[0].params["precision"]
     batched = args.workload == "channels"
+    if args.sequential and not batched:
+        raise SystemExit("--sequential applies to the batched workload")
     cells = sum(c.params["nx"] * c.params["ny"] for c in cases)
     print(f"[bench] {args.workload} instances={len(cases)} nodes={cells} precision={precision} "
           f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
-    if batched:
+    if batched and args.sequential:
+        # the same instances as separate lattices stepped one after another on
+        # one stream: the method without the batched launch
+        lat = _Sequential([olb.Lattice(c.params, device="cuda:0") for c in cases])
+        for one, c in zip(lat.lats, cases):
+            one.set_tile(args.tile)
+            one.set_fields(*c.fields)
+        n_stage, n_walls = 3, 3
+        tile_by = args.tile
+    elif batched:
         lat = olb.Batch([c.params for c in cases], device="cuda:0")
         if args.autotune:
             lat.autotune(trial_steps=2)
@@ -318,7 +358,7 @@ def main():
     vec_peak = FP64_VEC_PEAK_TFLOPS if precision == 0 else FP32_VEC_PEAK_TFLOPS
     hbm_frac = achieved_gbs / HBM_PEAK_GBS
     alu_frac = achieved_tflops / vec_peak
-    traffic = load_traffic(args.workload)
+    traffic = load_traffic(args.workload) if args.precision == "auto" and not args.sequential else None
     if alu_frac >= hbm_frac:
         roof = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": vec_peak,
                 "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": traffic,
@@ -351,6 +391,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "nodes": cells, "instances": len(cases), "tile": f"63x{tile_by - 1}",
+                   "precision": "fp64" if precision == 0 else "fp32-mixed",
+                   "launch": "sequential instances" if args.sequential else "one launch per stage",
                    "wall_s": round(wall, 3)},
         "roofline": roof,
         "cpu_baseline": cpu,

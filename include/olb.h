@@ -50,7 +50,11 @@ typedef enum {
   OLB_E_STATE = -7       /* call out of order (e.g. step before set_fields)     */
 } olb_status;
 
-enum { OLB_BC_PERIODIC = 0, OLB_BC_DIFFUSE = 1 };
+/* bc_y kinds: periodic; diffuse walls at both ends (Sec. 3.4.2); a specular
+ * symmetry plane at the low end (Sec. 3.4.1: ghost rows mirror the interior
+ * with p_y reversed) and a diffuse wall at the high end -- the half channel
+ * of the planar-interface test (Sec. 5).  bc_x must be periodic. */
+enum { OLB_BC_PERIODIC = 0, OLB_BC_DIFFUSE = 1, OLB_BC_SPECULAR_DIFFUSE = 2 };
 enum { OLB_FP64 = 0, OLB_FP32_MIXED = 1 };
 
 /* Problem statement of Secs. 2 and 3 of the paper:

@@ -241,3 +241,33 @@ def closure_moments(nx, ny, seed=11, amplitude=0.01) -> np.ndarray:
     U = 2.0 * uniform(seed, 4 * nx * ny).reshape(4, ny, nx) - 1.0
     return np.stack([N_CRIT * (1.0 + amplitude * U[0]), amplitude * U[1], amplitude * U[2],
                      0.85 * T_CRIT * (1.0 + amplitude * U[3])])
+
+
+# ------------------------------------------------ half channels (specular) --
+
+def half_channel(nx=8, ny=40, seed=9, tw=0.8 * T_CRIT, ds=1.0 / 320, dt=2e-4, tau=0.005, noise=0.01,
+                 temperature=None, **kw):
+    """Noisy vdW fluid between a specular symmetry plane (low y end) and a
+    diffuse wall at T_w (high y end)."""
+    U = uniform(seed, nx * ny).reshape(ny, nx)
+    n = N_CRIT * (1.0 + noise * (2.0 * U - 1.0))
+    z = np.zeros((ny, nx))
+    T = np.full((ny, nx), float(tw if temperature is None else temperature))
+    p = _params(nx, ny, ds, dt, tau, bc_y=2, tw=tw, **kw)
+    return Case(f"half{nx}x{ny}", p, n, z, z.copy(), T, 0)
+
+
+def planar_interface(tw, n_gas, n_liquid, cells=160, ds=1.0 / 320, dt=2e-4, tau=0.005, sigma=1e-4,
+                     a=9.0 / 8.0, b=1.0 / 3.0, x0=0.25):
+    """The planar-interface test (Sec. 5) on the half channel: one column of
+    `cells` nodes from the channel centre (specular plane) to the wall at
+    x = cells ds = 0.5, fluid at rest at T = T_w with the tanh profile of
+    Eq. tanh between the given gas and liquid densities, width Eq. xiwagner
+    (kappa = sigma), interface at x0 (the paper's walls are across x; here
+    across y)."""
+    xi = np.sqrt(8.0 * sigma / (9.0 * (1.0 - tw)))
+    y = (np.arange(cells) + 0.5) * ds
+    n = n_gas + 0.5 * (n_liquid - n_gas) * (1.0 + np.tanh((y - x0) / xi))
+    z = np.zeros((cells, 1))
+    p = _params(1, cells, ds, dt, tau, a=a, b=b, sigma=sigma, bc_y=2, tw=tw)
+    return Case(f"planar{tw:g}", p, n[:, None], z, z.copy(), np.full((cells, 1), float(tw)), 0)

@@ -344,13 +344,14 @@ int oolb_init(const oolb_params* p, oolb_ctx** out) {
   *out = NULL;
   if (p->nx < 1 || p->ny < 1) return OOLB_E_ARG;
   if (p->bc_x != OOLB_BC_PERIODIC) return OOLB_E_ARG;
-  if (p->bc_y != OOLB_BC_PERIODIC && p->bc_y != OOLB_BC_DIFFUSE) return OOLB_E_ARG;
-  if (p->bc_y == OOLB_BC_DIFFUSE && p->ny < 3) return OOLB_E_ARG;
+  if (p->bc_y != OOLB_BC_PERIODIC && p->bc_y != OOLB_BC_DIFFUSE && p->bc_y != OOLB_BC_SPECULAR_DIFFUSE)
+    return OOLB_E_ARG;
+  if (p->bc_y != OOLB_BC_PERIODIC && p->ny < 3) return OOLB_E_ARG;
   if (!(p->ds > 0.0) || !(p->dt > 0.0) || !isfinite(p->ds) || !isfinite(p->dt))
     return OOLB_E_ARG;
   if (!(p->sigma >= 0.0) || !(p->a >= 0.0) || !(p->b >= 0.0)) return OOLB_E_ARG;
   if (!(p->tau > 0.0)) return OOLB_E_DOMAIN;
-  if (p->bc_y == OOLB_BC_DIFFUSE && (!(p->tw_lo > 0.0) || !(p->tw_hi > 0.0)))
+  if (p->bc_y != OOLB_BC_PERIODIC && (!(p->tw_lo > 0.0) || !(p->tw_hi > 0.0)))
     return OOLB_E_DOMAIN;
   double R[5], W[5];
   oolb_quadrature(R, W);
@@ -511,9 +512,22 @@ static double mget(const oolb_ctx* c, const double* g, int x, int y) {
 static void fill_wall_ghosts(oolb_ctx* c, const double* f) {
   const int nx = c->nx, ny = c->ny;
   const size_t np = plane(c);
+  const int specular_lo = c->p.bc_y == OOLB_BC_SPECULAR_DIFFUSE;
 #pragma omp parallel for schedule(static)
   for (int x = 0; x < nx; ++x) {
     for (int wall = 0; wall < 2; ++wall) {
+      if (wall == 0 && specular_lo) {
+        /* Sec. 3.4.1: the ghost row -1 - j of population (kx, ky) holds
+         * row j of the population with the reversed y velocity, (kx, 4 - ky) */
+        for (int k = 0; k < KV; ++k) {
+          int kx = k % 5, ky = k / 5;
+          int km = 5 * (4 - ky) + kx;
+          for (int j = 0; j < 3; ++j)
+            c->glo[((size_t)k * 3 + j) * nx + x] = f[(size_t)km * np + (size_t)j * nx + x];
+        }
+        c->nwlo[x] = 0.0;
+        continue;
+      }
       /* wall = 0: lower wall at y = -1/2 (towards-wall: p_y < 0);
        * wall = 1: upper wall at y = ny - 1/2 (towards-wall: p_y > 0). */
       const double Tw = wall ? c->p.tw_hi : c->p.tw_lo;
@@ -578,7 +592,7 @@ static void fill_wall_ghosts(oolb_ctx* c, const double* f) {
 
 int oolb_wall_density(const oolb_ctx* c, double* nw_lo, double* nw_hi) {
   if (!c || !nw_lo || !nw_hi) return OOLB_E_ARG;
-  if (c->p.bc_y != OOLB_BC_DIFFUSE) return OOLB_E_STATE;
+  if (c->p.bc_y == OOLB_BC_PERIODIC) return OOLB_E_STATE;
   memcpy(nw_lo, c->nwlo, (size_t)c->nx * sizeof(double));
   memcpy(nw_hi, c->nwhi, (size_t)c->nx * sizeof(double));
   return OOLB_OK;
@@ -594,7 +608,7 @@ static void rhs(oolb_ctx* c, const double* f, double* L) {
   const oolb_params* P = &c->p;
 
   /* 1. ghosts of the current f (walls) */
-  if (P->bc_y == OOLB_BC_DIFFUSE) fill_wall_ghosts(c, f);
+  if (P->bc_y != OOLB_BC_PERIODIC) fill_wall_ghosts(c, f);
 
   /* 2. moments and Delta p = p^i - p^w at every node */
 #pragma omp parallel for schedule(static)

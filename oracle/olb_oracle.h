@@ -32,7 +32,10 @@ enum {
   OOLB_E_STATE = -7      /* call out of order (e.g. step before set_fields)   */
 };
 
-enum { OOLB_BC_PERIODIC = 0, OOLB_BC_DIFFUSE = 1 };
+/* bc_y: OOLB_BC_DIFFUSE = diffuse walls at both ends of y;
+ * OOLB_BC_SPECULAR_DIFFUSE = a specular symmetry plane at the low end (Sec.
+ * 3.4.1) and a diffuse wall at the high end (the half channel of Sec. 5). */
+enum { OOLB_BC_PERIODIC = 0, OOLB_BC_DIFFUSE = 1, OOLB_BC_SPECULAR_DIFFUSE = 2 };
 
 /* Problem statement (Sec. 2 and 3): lattice nx*ny of spacing ds, RK-3 step dt,
  * BGK relaxation time tau, EOS p^w = nT/(1-bn) - a n^2, surface-tension

@@ -15,7 +15,8 @@ namespace olbk {
 struct Geometry {
   int nx, ny;
   int64_t ps;      // plane stride in elements: (ny + 6) * nx
-  int walls;       // 1: diffuse walls across y, 0: periodic y
+  int walls;       // 0: periodic y; 1: diffuse walls across y; 2: specular
+                   // symmetry plane at the low end, diffuse wall at the high end
 };
 
 // One RK stage of one instance, as the tile function sees it.

@@ -601,6 +601,22 @@ __global__ void walls_kernel(const WallBatchArgs wa) {
   const double Tw = wall ? d.tw[1] : d.tw[0];
   const double uw = wall ? d.uw[1] : d.uw[0];
   const double rho0 = d.rho0;
+  if (wall == 0 && d.g.walls == 2) {
+    // specular symmetry plane (Sec. 3.4.1): ghost row -1 - j of population
+    // (kx, ky) is interior row j of (kx, 4 - ky); w_k is even in p_y, so the
+    // FP32 departure values mirror the same way
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+      const int km = 5 * (4 - k / 5) + k % 5;
+      const Real* src = f + km * ps + x;
+      Real* pk = f + k * ps + x;
+      pk[g1 * nx] = src[r0 * nx];
+      pk[g2 * nx] = src[r1 * nx];
+      pk[g3 * nx] = src[r2 * nx];
+    }
+    d.nw[x] = 0.0;
+    return;
+  }
 
   // populations travelling towards the wall (and p_y = 0): quadratic
   // extrapolation; their WENO flux through the wall face

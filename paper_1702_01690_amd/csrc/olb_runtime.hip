@@ -54,8 +54,10 @@ olb_status validate(const olb_params* p, std::string& why) {
   if (p->nx < 1 || p->ny < 1) { why = "nx, ny must be >= 1"; return OLB_E_ARG; }
   if ((int64_t)(p->ny + 6) * p->nx >= (int64_t)1 << 31) { why = "lattice too large"; return OLB_E_ARG; }
   if (p->bc_x != OLB_BC_PERIODIC) { why = "walls are supported across y only (bc_x must be periodic)"; return OLB_E_ARG; }
-  if (p->bc_y != OLB_BC_PERIODIC && p->bc_y != OLB_BC_DIFFUSE) { why = "bad bc_y"; return OLB_E_ARG; }
-  if (p->bc_y == OLB_BC_DIFFUSE && p->ny < 3) { why = "diffuse walls need ny >= 3"; return OLB_E_ARG; }
+  if (p->bc_y != OLB_BC_PERIODIC && p->bc_y != OLB_BC_DIFFUSE && p->bc_y != OLB_BC_SPECULAR_DIFFUSE) {
+    why = "bad bc_y"; return OLB_E_ARG;
+  }
+  if (p->bc_y != OLB_BC_PERIODIC && p->ny < 3) { why = "walls need ny >= 3"; return OLB_E_ARG; }
   if (p->precision != OLB_FP64 && p->precision != OLB_FP32_MIXED) { why = "bad precision"; return OLB_E_ARG; }
   if (!(p->ds > 0.0) || !(p->dt > 0.0) || !std::isfinite(p->ds) || !std::isfinite(p->dt)) {
     why = "ds, dt must be positive and finite"; return OLB_E_ARG;
@@ -68,7 +70,7 @@ olb_status validate(const olb_params* p, std::string& why) {
     why = "rho_ref must be positive for FP32 storage"; return OLB_E_ARG;
   }
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) { why = "tau must be positive"; return OLB_E_DOMAIN; }
-  if (p->bc_y == OLB_BC_DIFFUSE &&
+  if (p->bc_y != OLB_BC_PERIODIC &&
       (!(p->tw_lo > 0.0) || !(p->tw_hi > 0.0) || !std::isfinite(p->tw_lo) ||
        !std::isfinite(p->tw_hi) || !std::isfinite(p->uw_lo) || !std::isfinite(p->uw_hi))) {
     why = "wall temperatures must be positive"; return OLB_E_DOMAIN;
@@ -163,7 +165,7 @@ struct Engine {
     ws = (unsigned char*)workspace;
     ws_bytes = bytes;
     rb = p[0].precision == OLB_FP32_MIXED ? 4 : 8;
-    walls = p[0].bc_y == OLB_BC_DIFFUSE;
+    walls = p[0].bc_y != OLB_BC_PERIODIC;
     d_desc = (olbk::InstDesc*)ws;
     flag = (int*)(ws + align_up((size_t)n * sizeof(olbk::InstDesc)));
     size_t off = head_bytes(n);
@@ -175,7 +177,7 @@ struct Engine {
       d.g.nx = p[i].nx;
       d.g.ny = p[i].ny;
       d.g.ps = (int64_t)(p[i].ny + 6) * p[i].nx;
-      d.g.walls = walls;
+      d.g.walls = p[i].bc_y;  // 0 periodic, 1 diffuse walls, 2 specular low end + diffuse high wall
       for (int k = 0; k < 3; ++k) d.f[k] = ws + off + k * L.buf;
       d.carry[0] = (double*)(ws + off + 3 * L.buf);
       d.carry[1] = (double*)(ws + off + 3 * L.buf + L.carry);

@@ -77,6 +77,19 @@ def test_batch_fp64_matches_oracle_per_instance(kind):
         assert max(err.values()) < TOL64, (c.name, err)
 
 
+def test_batch_half_channels_match_oracle_per_instance():
+    cases = [I.half_channel(70, 20, seed=31, tw=0.75 * I.T_CRIT), I.half_channel(9, 33, seed=32),
+             I.half_channel(130, 7, seed=33, tw=0.9 * I.T_CRIT, uw=0.02)]
+    steps = 15
+    b = _batch(cases)
+    b.step(steps)
+    b.sync()
+    for i, c in enumerate(cases):
+        err = moment_errors(b.moments(i), _oracle_run(c, steps))
+        print(f"[batch] {c.name}: {err}", flush=True)
+        assert max(err.values()) < TOL64, (c.name, err)
+
+
 def test_batch_equals_single_instance_runs_bitwise():
     olb = _olb()
     cases = _channels()

@@ -48,7 +48,7 @@ def run_gpu(case, steps, precision=0, by=None, rho_ref=None):
     lat.sync()
     m = lat.moments()
     f = lat.get_f()
-    nw = lat.wall_density() if p.get("bc_y", 0) == 1 and steps > 0 else None
+    nw = lat.wall_density() if p.get("bc_y", 0) != 0 and steps > 0 else None
     lat.close()
     return m, f, nw
 
@@ -59,7 +59,7 @@ def _oracle_cached(name, steps):
     o = oracle.Oracle(case.params)
     o.set_fields(*case.fields)
     o.step(steps)
-    nw = o.wall_density() if case.params.get("bc_y", 0) == 1 and steps > 0 else None
+    nw = o.wall_density() if case.params.get("bc_y", 0) != 0 and steps > 0 else None
     return o.moments(), o.get_f(), nw
 
 
@@ -79,6 +79,8 @@ CASES = {
     "noisy70x37": lambda: _noisy_vdw(70, 37),
     "noisy5x3": lambda: _noisy_vdw(5, 3, seed=6),
     "channel67x20": lambda: I.channel(67, 20, tw=0.75 * I.T_CRIT, steps=30, seed=9),
+    "half40x70": lambda: I.half_channel(40, 70, seed=9, tw=0.8 * I.T_CRIT, temperature=I.T_CRIT),
+    "half67x9": lambda: I.half_channel(67, 9, seed=10, tw=0.75 * I.T_CRIT, uw=0.01),
 }
 
 
@@ -132,6 +134,46 @@ def test_fp64_diffuse_walls_match_oracle(name, steps):
     assert ferr < TOL64
     for g, o in zip(gnw, onw):
         assert rel_scalar(g, o) < TOL64
+
+
+@pytest.mark.parametrize("name,steps", [("half40x70", 20), ("half67x9", 30)])
+def test_fp64_specular_half_channel_matches_oracle(name, steps):
+    """Specular symmetry plane at the low end (Sec. 3.4.1), diffuse wall at
+    the high end."""
+    err, ferr, gnw, onw = _compare(name, steps)
+    assert max(err.values()) < TOL64, err
+    assert ferr < TOL64
+    assert np.all(gnw[0] == 0.0)
+    assert rel_scalar(gnw[1], onw[1]) < TOL64
+
+
+def test_fp32_specular_half_channel_density_within_1e5():
+    err, _, _, _ = _compare("half40x70", 10, precision=1)
+    assert err["n"] < 1e-5, err
+
+
+def test_half_channel_equals_mirror_symmetric_full_channel():
+    """The GPU half channel against the GPU full channel (diffuse walls at
+    both ends) started from mirror-symmetric fields: the upper half."""
+    olb = _olb()
+    nx, h = 70, 12
+    tw = 0.8 * I.T_CRIT
+    full = I.channel(nx, 2 * h, tw=tw, seed=21)
+    half = dict(full.params)
+    half.update(ny=h, bc_y=2)
+    lower = lambda a: a[:h][::-1]
+    fields = (np.vstack([lower(full.n), full.n[:h]]), np.vstack([lower(full.ux), full.ux[:h]]),
+              np.vstack([-lower(full.uy), full.uy[:h]]), np.vstack([lower(full.T), full.T[:h]]))
+    a, b = olb.Lattice(full.params), olb.Lattice(half)
+    a.set_fields(*fields)
+    b.set_fields(*(q[h:] for q in fields))
+    a.step(15)
+    b.step(15)
+    upper = tuple(m[h:] for m in a.moments())
+    err = moment_errors(b.moments(), upper)
+    print(f"[parity] half vs full channel: {err}", flush=True)
+    assert max(err.values()) < TOL64, err      # rounding order differs between the two tilings
+    assert rel_scalar(b.wall_density()[1], a.wall_density()[1]) < TOL64
 
 
 def test_fp64_channel_100_steps_within_rounding_amplification():

@@ -134,6 +134,49 @@ def test_diffuse_wall_moving_wall_drags_fluid():
     assert prof[-1] > prof[0] and prof[-1] > 1e-4 and abs(prof[0]) < prof[-1]
 
 
+def _mirror_symmetric(nx, h, seed):
+    """Fields on 2h rows symmetric about the plane between rows h-1 and h:
+    n, u_x, T even, u_y odd."""
+    n, ux, uy, T = _noisy(nx, h, seed, n0=1.2, t0=0.9)
+    up = lambda a: a[::-1]
+    return (np.vstack([up(n), n]), np.vstack([up(ux), ux]), np.vstack([-up(uy), uy]),
+            np.vstack([up(T), T]))
+
+
+@pytest.mark.parametrize("steps", [1, 12])
+def test_specular_half_channel_equals_mirror_symmetric_full_channel(steps):
+    """Sec. 3.4.1: a specular plane at the low end of a half channel gives the
+    upper half of the full channel (diffuse walls at both ends) started from
+    mirror-symmetric fields."""
+    nx, h, tw = 5, 9, 0.8
+    full = oracle.Oracle(_params(nx, 2 * h, bc_y=1, tw_lo=tw, tw_hi=tw, uw_lo=0.02, uw_hi=0.02))
+    half = oracle.Oracle(_params(nx, h, bc_y=2, tw_lo=tw, tw_hi=tw, uw_lo=0.02, uw_hi=0.02))
+    fields = _mirror_symmetric(nx, h, seed=71)
+    full.set_fields(*fields)
+    half.set_fields(*(a[h:] for a in fields))
+    full.step(steps)
+    half.step(steps)
+    mf, mh = full.moments(), half.moments()
+    for a, b in zip(mh, mf):
+        np.testing.assert_allclose(a, b[h:], rtol=1e-12, atol=1e-15)
+    # the full channel stays mirror symmetric; u_y changes sign
+    np.testing.assert_allclose(mf[0][:h][::-1], mf[0][h:], rtol=1e-12)
+    np.testing.assert_allclose(-mf[2][:h][::-1], mf[2][h:], rtol=1e-10, atol=1e-15)
+    lo, hi = half.wall_density()
+    flo, fhi = full.wall_density()
+    np.testing.assert_allclose(hi, fhi, rtol=1e-12)
+    assert np.all(lo == 0.0)
+
+
+def test_specular_half_channel_rest_state_is_a_fixed_point():
+    nx, ny, tw = 3, 7, 0.75
+    o = oracle.Oracle(_params(nx, ny, bc_y=2, tw_lo=tw, tw_hi=tw))
+    o.set_fields(np.full((ny, nx), 1.1), np.zeros((ny, nx)), np.zeros((ny, nx)), np.full((ny, nx), tw))
+    f0 = o.get_f()
+    o.step(6)
+    np.testing.assert_allclose(o.get_f(), f0, rtol=1e-13, atol=1e-16)
+
+
 # --------------------------------------------------- hydrodynamic limits --
 
 def _amplitude(u, x, k):

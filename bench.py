@@ -66,6 +66,9 @@ WORKLOADS = {
                     "n=3.5(1+-1% noise), tau=0.005, dt=2e-4, ds=1/320",
     "channels": "256 walled channels (nx 64..512, ny 128..1024, 43.6 M nodes), FP32-mixed, "
                 "T_w in [0.7, 0.95] T_c, one launch per stage over all channels, graphs of 10 steps",
+    "planar": "planar interface (Sec. 5): 13 half channels of 1x160 nodes (specular centre plane, diffuse "
+              "wall), a=9/8 b=1/3, T_w = 0.74..0.98, ds=1/320, dt=2e-4, tau=5e-3, sigma=1e-4, one batch "
+              "in HIP graphs, relaxed to the steady state",
     "closure": "learned closure: coarse 512x512 FP32-mixed (ds 1/80, dt 8e-4) corrected every 10 steps "
                "by the bf16 conv net, against fine 2048x2048 FP64 (ds 1/320, dt 2e-4); spinodal at "
                "T in [0.75, 0.95] T_c, n = 3.5(1 +- 1% noise), tau = 0.005; 200 coarse steps",
@@ -136,6 +139,74 @@ def copy_kernel(gib, reps=10):
     moved = 2 * n * 8
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
                       "copy_GBps": round(moved / secs / 1e9, 1), "reps": reps}))
+
+
+def run_planar(args):
+    """Phase diagram of the solver: a batch of half channels, one per wall
+    temperature, relaxed to the steady state; coexistence densities against
+    the Maxwell construction, spurious velocity and heating."""
+    import torch
+    import olb_inputs as I
+    from paper_1702_01690_amd import olb, phase
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    temps = [round(0.74 + 0.02 * i, 2) for i in range(13)]
+    maxwell = [phase.maxwell_coexistence(t) for t in temps]
+    cases = [I.planar_interface(t, ng, nl) for t, (ng, nl) in zip(temps, maxwell)]
+    b = olb.Batch([c.params for c in cases], device="cuda:0")
+    b.use_graph(10)
+    for i, c in enumerate(cases):
+        b.set_fields(i, *c.fields)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(b.stream)
+    steps, change = phase.relax(b, chunk=20000, rtol=1e-7, max_steps=args.planar_steps, log=log)
+    ev1.record(b.stream)
+    b.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    secs = ev0.elapsed_time(ev1) / 1e3
+    cells = sum(c.params["nx"] * c.params["ny"] for c in cases)
+    rows = []
+    for i, t in enumerate(temps):
+        m = b.moments(i)
+        ng, nl = phase.coexistence(m[0])
+        u, dT = phase.spurious(m, t)
+        rows.append({"T_w": t, "n_g": ng, "n_l": nl,
+                     "n_g_vs_maxwell": (ng - maxwell[i][0]) / maxwell[i][0],
+                     "n_l_vs_maxwell": (nl - maxwell[i][1]) / maxwell[i][1],
+                     "max_u": u, "max_T_minus_Tw": dT})
+        log(f"T_w {t}: n_g {ng:.7f} ({rows[-1]['n_g_vs_maxwell']:+.2e}), n_l {nl:.7f} "
+            f"({rows[-1]['n_l_vs_maxwell']:+.2e}), |u| {u:.2e}, dT {dT:.2e}")
+    mlups = cells * steps / secs / 1e6
+    launch_s = secs / (3 * steps)
+    achieved = ALG_VALUES_PER_CELL_STEP * 8 * cells / 3 / launch_s / 1e9
+    out = {
+        "metric": "MLUPS per full RK3 step (D2Q25)",
+        "value": round(mlups, 3),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": round(secs / steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "planar", "description": WORKLOADS["planar"], "nodes": cells,
+                   "instances": len(cases), "final_relative_change_per_20000_steps": change,
+                   "wall_s": round(wall, 2), "phase_diagram": rows,
+                   "note": "1-D columns of 160 nodes: a launch is one tile column per instance, "
+                           "so the step time is the latency of one tile, not bandwidth"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 7), "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
 
 
 def run_closure(args):
@@ -269,6 +340,8 @@ def main():
                     help="override the workload's storage precision (speedup comparisons)")
     ap.add_argument("--sequential", action="store_true",
                     help="batched workload: step the instances as separate lattices, one after another")
+    ap.add_argument("--planar-steps", type=int, default=600000,
+                    help="step limit of the planar-interface relaxation")
     ap.add_argument("--closure-samples", type=int, default=64,
                     help="training trajectories of the closure workload (8 pairs each)")
     ap.add_argument("--closure-epochs", type=int, default=30)
@@ -285,6 +358,9 @@ def main():
 
     if args.workload == "closure":
         run_closure(args)
+        return
+    if args.workload == "planar":
+        run_planar(args)
         return
 
     import torch

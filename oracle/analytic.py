@@ -33,6 +33,10 @@ def maxwell(T, a=9.0 / 8.0, b=1.0 / 3.0):
 
     guess = [0.5 * ns_lo, min(0.5 * (ns_hi + nmax), nmax * 0.99)]
     sol = optimize.fsolve(residual, guess, xtol=1e-12)
+    # the Newton iteration from this guess can collapse onto the trivial
+    # solution n_g = n_l far below T_c: refuse rather than return it
+    if not (0.0 < sol[0] < ns_lo and ns_hi < sol[1] < nmax):
+        raise RuntimeError(f"Maxwell construction did not converge at T = {T}")
     return float(sol[0]), float(sol[1])
 
 

@@ -43,3 +43,40 @@ def spurious(moments, tw):
     """Largest speed and largest temperature excess T - T_w of a profile."""
     n, ux, uy, T = (np.asarray(a) for a in moments)
     return float(np.max(np.hypot(ux, uy))), float(np.max(T - tw))
+
+
+def _pressure(n, T, a, b):
+    return n * T / (1.0 - b * n) - a * n * n
+
+
+def _chemical_potential(n, T, a, b):
+    # mu = dF/dn of the free energy density F = n T [ln(n / (1 - b n)) - 1] - a n^2
+    # (m = k_B = 1); p = n mu - F reproduces Eq. vdw
+    return T * (np.log(n / (1.0 - b * n)) + b * n / (1.0 - b * n)) - 2.0 * a * n
+
+
+def maxwell_coexistence(T, a=9.0 / 8.0, b=1.0 / 3.0):
+    """Gas and liquid densities of the van der Waals fluid (Eq. vdw) at
+    T < T_c = 8a / (27b): equal pressure and equal chemical potential (the
+    Maxwell construction).  The steady momentum balance of the paper's force,
+    grad p^w = sigma n grad lap n, imposes exactly these two conditions
+    between the bulk phases of a planar interface."""
+    from scipy.optimize import brentq
+    nc, nmax = 1.0 / (3.0 * b), 1.0 / b
+    if not T < 8.0 * a / (27.0 * b):
+        raise ValueError("temperature at or above the critical point")
+    eps = 1e-12 * nmax
+    # spinodal points: dp/dn = T / (1 - b n)^2 - 2 a n = 0 on either side of n_c
+    dp = lambda n: T / (1.0 - b * n) ** 2 - 2.0 * a * n
+    s1 = brentq(dp, eps, nc)
+    s2 = brentq(dp, nc, nmax - eps)
+    p_min = _pressure(s2, T, a, b)
+    lo = brentq(lambda n: _pressure(n, T, a, b) - p_min, eps, s1) if p_min > 0.0 else eps
+
+    def liquid(ng):
+        pg = _pressure(ng, T, a, b)
+        return brentq(lambda n: _pressure(n, T, a, b) - pg, s2, nmax - eps)
+
+    gap = lambda ng: _chemical_potential(ng, T, a, b) - _chemical_potential(liquid(ng), T, a, b)
+    ng = brentq(gap, lo * (1.0 + 1e-9) + 1e-300, s1 * (1.0 - 1e-9), xtol=1e-15, rtol=1e-14)
+    return float(ng), float(liquid(ng))

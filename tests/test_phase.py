@@ -1,0 +1,41 @@
+"""The package's coexistence solver (equal pressure and equal chemical
+potential of the vdW free energy) against the oracle's equal-area Maxwell
+construction and the densities the paper prints (Sec. 5).  CPU only."""
+import numpy as np
+import pytest
+
+import olb_inputs as I
+from conftest import golden
+from oracle import analytic
+from paper_1702_01690_amd import phase
+
+
+@pytest.mark.parametrize("T", [0.74, 0.8, 0.85, 0.9, 0.95, 0.99])
+def test_coexistence_equals_equal_area_construction(T):
+    ng, nl = phase.maxwell_coexistence(T)
+    rg, rl = analytic.maxwell(T)
+    assert abs(ng - rg) <= 1e-11 * rg and abs(nl - rl) <= 1e-11 * rl
+
+
+def test_coexistence_reproduces_printed_values_and_other_units():
+    g = golden("eos_values.json")
+    ng, nl = phase.maxwell_coexistence(0.8)
+    m = g["maxwell_T08"]
+    assert abs(ng - m["n_g"]) < 5e-7
+    assert abs(nl - m["n_l"]) < m["tol_n_l"]
+    # a = 9/49, b = 2/21 scales densities by 3.5 and temperatures by 4/7
+    ng2, nl2 = phase.maxwell_coexistence(0.9 * I.T_CRIT, I.VDW_A, I.VDW_B)
+    ng1, nl1 = phase.maxwell_coexistence(0.9)
+    assert abs(ng2 - 3.5 * ng1) < 1e-11 and abs(nl2 - 3.5 * nl1) < 1e-10
+
+
+def test_coexistence_far_below_the_critical_point():
+    # equal pressure and chemical potential hold at the returned pair
+    for T in (0.3, 0.5):
+        ng, nl = phase.maxwell_coexistence(T)
+        assert ng < nl
+        p = lambda n: phase._pressure(n, T, 9 / 8, 1 / 3)
+        mu = lambda n: phase._chemical_potential(n, T, 9 / 8, 1 / 3)
+        assert abs(p(ng) - p(nl)) < 1e-12 and abs(mu(ng) - mu(nl)) < 1e-12
+    with pytest.raises(ValueError):
+        phase.maxwell_coexistence(1.0)

@@ -66,6 +66,9 @@ WORKLOADS = {
                     "n=3.5(1+-1% noise), tau=0.005, dt=2e-4, ds=1/320",
     "channels": "256 walled channels (nx 64..512, ny 128..1024, 43.6 M nodes), FP32-mixed, "
                 "T_w in [0.7, 0.95] T_c, one launch per stage over all channels, graphs of 10 steps",
+    "quench": "phase separation between suddenly cooled plates (Sec. 7): 320x640 FP64 (walls across y), "
+              "a=9/8 b=1/3, fluid at T=1 with n = 1 +- 1%, walls at T_w=0.8, ds=1/320, dt=2e-4, tau=5e-3, "
+              "sigma=1e-4, to t = 25",
     "planar": "planar interface (Sec. 5): 13 half channels of 1x160 nodes (specular centre plane, diffuse "
               "wall), a=9/8 b=1/3, T_w = 0.74..0.98, ds=1/320, dt=2e-4, tau=5e-3, sigma=1e-4, one batch "
               "in HIP graphs, relaxed to the steady state",
@@ -139,6 +142,58 @@ def copy_kernel(gib, reps=10):
     moved = 2 * n * 8
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
                       "copy_GBps": round(moved / secs / 1e9, 1), "reps": reps}))
+
+
+def run_quench(args):
+    """The cooled-plates quench to t = 25, timed, with the checks of the
+    paper's description at t = 2.5, 5, 10, 12.5 and 25."""
+    import torch
+    import olb_inputs as I
+    from paper_1702_01690_amd import olb, phase
+
+    c = I.quench()
+    tw, dt = c.params["tw_lo"], c.params["dt"]
+    lat = olb.Lattice(c.params, device="cuda:0")
+    lat.set_fields(*c.fields)
+    m0 = float(c.n.sum())
+    _, n_liq = phase.maxwell_coexistence(tw)
+    snaps, done, secs = [], 0, 0.0
+    for t in (2.5, 5.0, 10.0, 12.5, 25.0):
+        k = int(round(t / dt)) - done
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(lat.stream)
+        lat.step(k)
+        ev1.record(lat.stream)
+        lat.sync()
+        secs += ev0.elapsed_time(ev1) / 1e3
+        done += k
+        n, ux, uy, T = lat.moments()
+        ny = n.shape[0]
+        pn, pT = n.mean(axis=1), T.mean(axis=1)
+        snaps.append({"t": t, "mass_drift": float((n.sum() - m0) / m0),
+                      "wall_film_n": float(0.5 * (pn[:5].mean() + pn[-5:].mean())),
+                      "centre_T": float(pT[ny // 2 - 5: ny // 2 + 5].mean()), "mean_T": float(T.mean()),
+                      "hottest_row_from_wall": int(min(np.argmax(pT[: ny // 2]),
+                                                       np.argmax(pT[ny // 2:][::-1]))),
+                      "n_min": float(n.min()), "n_max": float(n.max()),
+                      "max_speed": float(np.hypot(ux, uy).max())})
+        print(f"[bench] {snaps[-1]}", file=sys.stderr, flush=True)
+    cells = c.params["nx"] * c.params["ny"]
+    mlups = cells * done / secs / 1e6
+    achieved = ALG_VALUES_PER_CELL_STEP * 8 * cells * done / secs / 1e9
+    out = {
+        "metric": "MLUPS per full RK3 step (D2Q25)",
+        "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": done, "warmup": 0,
+        "ms_per_step": round(secs / done * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "quench", "description": WORKLOADS["quench"], "nodes": cells,
+                   "maxwell_liquid_density": n_liq, "snapshots": snaps,
+                   "timed": "stepping only (read-outs between snapshots excluded)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
 
 
 def run_planar(args):
@@ -361,6 +416,9 @@ def main():
         return
     if args.workload == "planar":
         run_planar(args)
+        return
+    if args.workload == "quench":
+        run_quench(args)
         return
 
     import torch

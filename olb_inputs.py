@@ -271,3 +271,16 @@ def planar_interface(tw, n_gas, n_liquid, cells=160, ds=1.0 / 320, dt=2e-4, tau=
     z = np.zeros((cells, 1))
     p = _params(1, cells, ds, dt, tau, a=a, b=b, sigma=sigma, bc_y=2, tw=tw)
     return Case(f"planar{tw:g}", p, n[:, None], z, z.copy(), np.full((cells, 1), float(tw)), 0)
+
+
+def quench(N=320, seed=17, tw=0.8, noise=0.01, dt=2e-4, tau=0.005, sigma=1e-4, a=9.0 / 8.0, b=1.0 / 3.0):
+    """Phase separation between suddenly cooled plates (Sec. 7): a vdW fluid
+    (a = 9/8, b = 1/3, T_c = n_c = 1) at rest at T = 1 with n = 1 + 0.01 (2U - 1)
+    between diffuse walls at T_w, 2N nodes across the walls and N along them,
+    ds = 1/N.  The paper's walls are across x; here across y (nx = N periodic,
+    ny = 2N)."""
+    U = uniform(seed, 2 * N * N).reshape(2 * N, N)
+    n = 1.0 + noise * (2.0 * U - 1.0)
+    z = np.zeros((2 * N, N))
+    p = _params(N, 2 * N, 1.0 / N, dt, tau, a=a, b=b, sigma=sigma, bc_y=1, tw=tw)
+    return Case(f"quench{N}", p, n, z, z.copy(), np.ones((2 * N, N)), 0)

@@ -72,6 +72,9 @@ WORKLOADS = {
     "planar": "planar interface (Sec. 5): 13 half channels of 1x160 nodes (specular centre plane, diffuse "
               "wall), a=9/8 b=1/3, T_w = 0.74..0.98, ds=1/320, dt=2e-4, tau=5e-3, sigma=1e-4, one batch "
               "in HIP graphs, relaxed to the steady state",
+    "galilei": "shear waves seen from a moving frame (Sec. 6.1): ideal gas (n=1) and vdW vapour / liquid "
+               "(a=9/8 b=1/3, coexistence densities at T0=0.8), N_x = 20..60 periodic, V = 0..2 step 0.1, "
+               "u0=1e-3, tau=5e-4, dt=2e-4; 315 instances in one batch, 2e5 steps, amplitude every 1000 steps",
     "closure": "learned closure: coarse 512x512 FP32-mixed (ds 1/80, dt 8e-4) corrected every 10 steps "
                "by the bf16 conv net, against fine 2048x2048 FP64 (ds 1/320, dt 2e-4); spinodal at "
                "T in [0.75, 0.95] T_c, n = 3.5(1 +- 1% noise), tau = 0.005; 200 coarse steps",
@@ -191,6 +194,54 @@ def run_quench(args):
                    "timed": "stepping only (read-outs between snapshots excluded)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
+def run_galilei(args):
+    """The Galilean shear-wave sweep behind the paper's two exponent tables:
+    every (medium, N_x, V) run as one instance of a batch; the exponents of
+    dx and of V from the sampled amplitudes."""
+    import olb_inputs as I
+    from paper_1702_01690_amd import galilei as G, phase
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    T0, tau, dt, u0 = 0.8, 5e-4, 2e-4, 1e-3
+    ng, nl = phase.maxwell_coexistence(T0)
+    media = {"ideal": (1.0, 0.0, 0.0, 0.0), "vapour": (ng, 9 / 8, 1 / 3, 1e-4),
+             "liquid": (nl, 9 / 8, 1 / 3, 1e-4)}
+    sizes = (20, 30, 40, 50, 60)
+    speeds = tuple(round(0.1 * i, 1) for i in range(21))
+    keys = [(m, N, V) for m in media for N in sizes for V in speeds]
+    cases = [I.shear_wave(N, V, *media[m], T0=T0, tau=tau, dt=dt, u0=u0) for m, N, V in keys]
+    log(f"galilei: {len(cases)} instances")
+    t0 = time.perf_counter()
+    times, amps, secs = G.sweep(cases, samples=200, every=1000, graph=args.graph or 10, log=log)
+    wall = time.perf_counter() - t0
+    res = {k: (G.viscosity_ratio(a, times, u0, tau, T0), G.l2_norm(a, times, u0, tau, T0))
+           for k, a in zip(keys, amps)}
+    dx, vv = G.orders(res, tuple(media), sizes)
+    steps = 200 * 1000
+    cells = sum(N for _, N, _ in keys)
+    mlups = cells * steps / secs / 1e6
+    achieved = ALG_VALUES_PER_CELL_STEP * 8 * cells * steps / secs / 1e9
+    out = {
+        "metric": "MLUPS per full RK3 step (D2Q25)",
+        "value": round(mlups, 3), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(secs / steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "galilei", "description": WORKLOADS["galilei"], "nodes": cells,
+                   "instances": len(cases), "wall_s": round(wall, 2),
+                   "timed": "stepping only (amplitude read-outs excluded)",
+                   "dx_orders": {m: {str(V): [round(x, 6) for x in v] for V, v in dx[m].items()} for m in dx},
+                   "v_orders": {m: {str(N): [round(x, 6) for x in v] for N, v in vv[m].items()} for m in vv},
+                   "note": "1 x N_x lattices: a launch is one tile per instance, so the step time is "
+                           "launch latency, not bandwidth"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 7), "traffic": None},
         "cpu_baseline": None,
     }
     print(json.dumps(out))
@@ -419,6 +470,9 @@ def main():
         return
     if args.workload == "quench":
         run_quench(args)
+        return
+    if args.workload == "galilei":
+        run_galilei(args)
         return
 
     import torch

@@ -284,3 +284,18 @@ def quench(N=320, seed=17, tw=0.8, noise=0.01, dt=2e-4, tau=0.005, sigma=1e-4, a
     z = np.zeros((2 * N, N))
     p = _params(N, 2 * N, 1.0 / N, dt, tau, a=a, b=b, sigma=sigma, bc_y=1, tw=tw)
     return Case(f"quench{N}", p, n, z, z.copy(), np.ones((2 * N, N)), 0)
+
+
+def shear_wave(N, V=0.0, n0=1.0, a=0.0, b=0.0, sigma=0.0, T0=0.8, tau=5e-4, dt=2e-4, u0=1e-3):
+    """Damping of a shear wave seen from a moving frame (Sec. 6.1): L = 1
+    periodic in x with N nodes (one node across y), n = n0, T = T0, u_x = V,
+    u_y = u0 sin(2 pi x_i) at the cell centres x_i = (i + 1/2)/N - 1/2
+    (0-based i).  a = b = sigma = 0 is the ideal gas; the vdW vapour and
+    liquid take their coexistence densities at T0 as n0."""
+    x = (np.arange(N) + 0.5) / N - 0.5
+    n = np.full((1, N), float(n0))
+    ux = np.full((1, N), float(V))
+    uy = (u0 * np.sin(2.0 * np.pi * x))[None, :]
+    T = np.full((1, N), float(T0))
+    p = _params(N, 1, 1.0 / N, dt, tau, a=a, b=b, sigma=sigma)
+    return Case(f"shear{N}_V{V:g}", p, n, ux, uy, T, 0, extra={"V": float(V), "u0": float(u0), "x": x})

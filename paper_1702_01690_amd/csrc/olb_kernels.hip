@@ -24,6 +24,29 @@
 namespace olbk {
 using namespace olbc;
 
+// Global-memory views of pointers that reach a kernel through a descriptor
+// in memory (the compiler cannot prove their address space and would emit
+// flat accesses, which share the LDS wait counter: every wait for an LDS read
+// would then also wait for all loads in flight).
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T>* as_global(T* p) {
+  return (gmem<T>*)p;
+}
+
+// Value held by lane + 1 of the wavefront (lane 63 receives 0): a DPP
+// wavefront shift by one lane, a VALU move rather than an LDS round trip.
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 __device__ __forceinline__ int wrapi(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;
@@ -282,10 +305,35 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
 
   // no __restrict__: in the last RK stage f^n and f_dst are the same array
   // (each node's f^n is read before its f_dst is written, by the same thread)
-  const Real* src = reinterpret_cast<const Real*>(a.fsrc);
-  const Real* fnp = reinterpret_cast<const Real*>(a.fn);
-  Real* dst = reinterpret_cast<Real*>(a.fdst);
+  const gmem<const Real>* src = as_global(reinterpret_cast<const Real*>(a.fsrc));
+  const gmem<const Real>* fnp = as_global(reinterpret_cast<const Real*>(a.fn));
+  gmem<Real>* dst = as_global(reinterpret_cast<Real*>(a.fdst));
+  const gmem<const double>* cin = as_global(a.cin);
+  gmem<double>* cout = as_global(a.cout);
 
+  constexpr int G = pop_group<Real>();
+  constexpr int NB = 2 * G;
+  constexpr int PF = prefetch_depth<Real>() - 1;
+  static_assert(PF >= G, "the register ring must hold the next group");
+  auto tile_pop = [](int t) { return t < 12 ? t : t + 1; };
+  const bool use_fn = a.A != 0.0;
+  // Loads issued before anything waits: the first group of planes, the
+  // register ring behind it and this node's f^n (the RK base, folded into the
+  // accumulators below).  Their latency hides behind the force stencils
+  // instead of stalling the start of the population stream and the end of
+  // the tile.  (Slots past the tile read a clamped, valid address.)
+  Real pre0[G][SLOTS], pre[PF][SLOTS];
+#pragma unroll
+  for (int j = 0; j < G; ++j)
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) pre0[j][s] = src[tile_pop(j) * ps + soff[s]];
+#pragma unroll
+  for (int t = G; t < G + PF; ++t)
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[tile_pop(t) * ps + soff[s]];
+  Real fnv[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) fnv[k] = use_fn ? fnp[k * ps + own] : (Real)0;
   // carried n and Delta p of f_src, tile + halo
   {
     const int64_t N = (int64_t)nx * ny;
@@ -293,8 +341,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     for (int s = 0; s < SLOTS; ++s) {
       const int i = tid + s * NT;
       if (i < TN) {
-        mn[i] = a.cin[moff[s]];
-        mp[i] = a.cin[N + moff[s]];
+        mn[i] = cin[moff[s]];
+        mp[i] = cin[N + moff[s]];
       }
     }
   }
@@ -348,12 +396,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   const Real cx = (Real)(-Bdt * Fx), cy = (Real)(-Bdt * Fy);
   const Real cb = (Real)(a.B * (1.0 - a.dt * a.inv_tau));
   const Real cadv = (Real)(-Bdt * a.inv_ds);
+  const Real rA = (Real)a.A;
   Real acc[25];
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
     // FP32 departure storage: M applied to the base w rho0 gives -p w rho0
     acc[k] = F32 ? (Real)(Bdt * a.rho0 * (Fx * Rk[k % 5] + Fy * Rk[k / 5]) * Wk[k % 5] * Wk[k / 5])
                  : (Real)0;
+    acc[k] += rA * fnv[k];
   }
 
   __syncthreads();  // the macroscopic tile is dead; its LDS becomes the planes
@@ -364,26 +414,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   // registers (ring of PF slots); one barrier per group.  Per population, the
   // contributions that do not need the upper face are accumulated before the
   // barrier, the y-advection after it.
-  constexpr int G = pop_group<Real>();
-  constexpr int NB = 2 * G;
-  constexpr int PF = prefetch_depth<Real>() - 1;
-  static_assert(PF >= G, "the register ring must hold the next group");
-  auto tile_pop = [](int t) { return t < 12 ? t : t + 1; };
   auto plane = [&](int t) { return pl0 + (t % NB) * TN; };
-  Real pre[PF][SLOTS];
-  {
 #pragma unroll
-    for (int j = 0; j < G; ++j)
+  for (int j = 0; j < G; ++j)
 #pragma unroll
-      for (int s = 0; s < SLOTS; ++s) {
-        const int i = tid + s * NT;
-        if (i < TN) plane(j)[i] = src[tile_pop(j) * ps + soff[s]];
-      }
-#pragma unroll
-    for (int t = G; t < G + PF; ++t)
-#pragma unroll
-      for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[tile_pop(t) * ps + soff[s]];
-  }
+    for (int s = 0; s < SLOTS; ++s) {
+      const int i = tid + s * NT;
+      if (i < TN) plane(j)[i] = pre0[j][s];
+    }
   __syncthreads();
 
   double sn = 0.0, sjx = 0.0, sjy = 0.0, se = 0.0;   // moments of f_src
@@ -402,6 +440,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     for (int i = 0; i < 5; ++i) {
       acc[5 * ky + i] += (Real)MT.v[i][kx] * tfx;
       acc[5 * i + kx] += (Real)MT.v[i][ky] * tfy;
+    }
+  };
+
+  // y-advection of group tg once the upper faces (written by the next wave)
+  // are visible
+  auto finish_y = [&](int tg, const Real* advx, const Real* ryl) {
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int t = tg + j, k = tile_pop(t);
+      const int ky = k / 5;
+      Real adv = advx[j];
+      if (ky != 2) {
+        const Real ryt = fy_sh[t % NB][ty < BY - 1 ? ty + 1 : ty][tx];
+        adv += (Real)Rk[ky] * (ryt - ryl[j]);
+      }
+      acc[k] += cadv * adv;
     }
   };
 
@@ -439,29 +493,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
                    c4 = P[rowc + 4], c5 = P[rowc + 5];
         rxl = px > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
       }
-      __builtin_amdgcn_sched_barrier(0);
       if (ky != 2) {
         const Real c0 = P[colc], c1 = P[colc + TW], c2 = P[colc + 2 * TW], c3 = P[colc + 3 * TW],
                    c4 = P[colc + 4 * TW], c5 = P[colc + 5 * TW];
         ryl[j] = py > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
         fy_sh[t % NB][ty][tx] = ryl[j];
       }
-      const Real rxr = (kx != 2) ? __shfl_down(rxl, 1) : (Real)0;
+      const Real rxr = (kx != 2) ? lane_next(rxl) : (Real)0;
       advx[j] = (kx != 2) ? (Real)px * (rxr - rxl) : (Real)0;
       local_terms(k, fk);
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const int t = t0 + j, k = tile_pop(t);
-      const int ky = k / 5;
-      Real adv = advx[j];
-      if (ky != 2) {
-        const Real ryt = fy_sh[t % NB][ty < BY - 1 ? ty + 1 : ty][tx];
-        adv += (Real)Rk[ky] * (ryt - ryl[j]);
-      }
-      acc[k] += cadv * adv;
-    }
+    finish_y(t0, advx, ryl);
     // do the updates now: left alone, the compiler sinks them to the end of
     // the kernel and keeps every population's inputs live until then
 #pragma unroll
@@ -482,8 +525,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   hfac(uy, T - 1.0, hy);
   const double cfe = Bdt * a.inv_tau;
   const double dn0 = sn - a.rho0;
-  const Real rA = (Real)a.A;
-  const bool use_fn = a.A != 0.0;
   double dn = 0.0, djx = 0.0, djy = 0.0, de = 0.0;
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
@@ -494,8 +535,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
                   (dn0 * (1.0 + hx[kx]) * (1.0 + hy[ky]) + a.rho0 * (hx[kx] + hy[ky] + hx[kx] * hy[ky])));
     else
       fe = (Real)(cfe * (sn * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky]))));
-    const Real fnk = use_fn ? fnp[k * ps + own] : (Real)0;
-    const Real out = rA * fnk + (acc[k] + fe);
+    const Real out = acc[k] + fe;
     if (active) dst[k * ps + own] = out;
     carry_add(k, (double)out, dn, djx, djy, de);
   }
@@ -505,8 +545,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     carry_finish<F32>(dn, djx, djy, de, a.rho0, a.a, a.b, cn, cdp);
     const int64_t N = (int64_t)nx * ny;
     const int m = y * nx + x;
-    a.cout[m] = cn;
-    a.cout[N + m] = cdp;
+    cout[m] = cn;
+    cout[N + m] = cdp;
     if (!(fabs(cn) < INFINITY)) a.flag[0] = 1;
   }
 }
@@ -525,9 +565,10 @@ __device__ __forceinline__ int find_instance(const InstDesc* inst, int ninst, in
 // one tile per workgroup.  Consecutive workgroups are dispatched to different
 // XCDs, so workgroup b takes tile (b mod 8) * ceil(T/8) + b / 8 (each XCD
 // works through a contiguous run of the queue).  Within an instance tiles are
-// numbered row by row: the workgroups an XCD runs at once cover whole tile
-// rows, whose shared x-halos and the next row's y-halos meet in its L2
-// (measured faster than column-by-column order on 2048^2).
+// numbered row by row inside strips of ba.strip tile columns (whole rows when
+// 0): an XCD then runs vertically adjacent tiles close together in time, so
+// the halo rows they share are still in its L2 (in row order a tile's lower
+// neighbour starts about half a tile lifetime later and misses them).
 template <typename Real, int BY, bool WALLS>
 __global__ void __launch_bounds__(64 * BY, min_waves_per_simd<Real>()) stage_kernel(const BatchArgs ba) {
   __shared__ StageLds<Real, BY> sm;

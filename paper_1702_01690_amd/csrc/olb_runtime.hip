@@ -110,7 +110,7 @@ struct Engine {
   int rb = 8;
   bool walls = false;
   int by = 8;
-  int strip = 0;                   // tile order (BatchArgs::strip)
+  int strip = 8;                   // tile order (BatchArgs::strip)
   int cur = 0;                     // carry index of the current f^n
   int total_tiles = 0, wall_blocks = 0;
   int graph_steps = 0;             // 0: direct launches

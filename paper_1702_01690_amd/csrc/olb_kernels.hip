@@ -257,7 +257,7 @@ constexpr int min_waves_per_simd() { return std::is_same<Real, float>::value ? O
 template <typename Real>
 constexpr int prefetch_depth() { return std::is_same<Real, float>::value ? OLB_PREFETCH32 : OLB_PREFETCH64; }
 
-template <typename Real, int BY, bool WALLS>
+template <typename Real, int BY, bool WALLS, bool FN>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, const int y0,
                                            StageLds<Real, BY>& sm) {
   constexpr bool F32 = std::is_same<Real, float>::value;
@@ -316,7 +316,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   constexpr int PF = prefetch_depth<Real>() - 1;
   static_assert(PF >= G, "the register ring must hold the next group");
   auto tile_pop = [](int t) { return t < 12 ? t : t + 1; };
-  const bool use_fn = a.A != 0.0;
+  // FN: the stage has an RK base term A f^n (A != 0); a template parameter so
+  // that the load counts the waits below rely on are known at compile time
+  constexpr bool use_fn = FN;
+  // the carried fields first: memory reads complete in issue order, so the
+  // force stencils wait for these alone while the loads below are in flight
+  double cn_in[SLOTS], cp_in[SLOTS];
+  {
+    const int64_t N = (int64_t)nx * ny;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      cn_in[s] = cin[moff[s]];
+      cp_in[s] = cin[N + moff[s]];
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);   // keep them ahead of the loads below
   // Loads issued before anything waits: the first group of planes, the
   // register ring behind it and this node's f^n (the RK base, folded into the
   // accumulators below).  Their latency hides behind the force stencils
@@ -334,15 +348,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   Real fnv[25];
 #pragma unroll
   for (int k = 0; k < 25; ++k) fnv[k] = use_fn ? fnp[k * ps + own] : (Real)0;
-  // carried n and Delta p of f_src, tile + halo
+  // carried n and Delta p of f_src, tile + halo, into LDS
   {
-    const int64_t N = (int64_t)nx * ny;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int i = tid + s * NT;
       if (i < TN) {
-        mn[i] = cin[moff[s]];
-        mp[i] = cin[N + moff[s]];
+        mn[i] = cn_in[s];
+        mp[i] = cp_in[s];
       }
     }
   }
@@ -403,7 +416,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     // FP32 departure storage: M applied to the base w rho0 gives -p w rho0
     acc[k] = F32 ? (Real)(Bdt * a.rho0 * (Fx * Rk[k % 5] + Fy * Rk[k / 5]) * Wk[k % 5] * Wk[k / 5])
                  : (Real)0;
-    acc[k] += rA * fnv[k];
+    if (use_fn) acc[k] += rA * fnv[k];
   }
 
   __syncthreads();  // the macroscopic tile is dead; its LDS becomes the planes
@@ -569,7 +582,7 @@ __device__ __forceinline__ int find_instance(const InstDesc* inst, int ninst, in
 // 0): an XCD then runs vertically adjacent tiles close together in time, so
 // the halo rows they share are still in its L2 (in row order a tile's lower
 // neighbour starts about half a tile lifetime later and misses them).
-template <typename Real, int BY, bool WALLS>
+template <typename Real, int BY, bool WALLS, bool FN>
 __global__ void __launch_bounds__(64 * BY, min_waves_per_simd<Real>()) stage_kernel(const BatchArgs ba) {
   __shared__ StageLds<Real, BY> sm;
   const int bid = blockIdx.x;
@@ -612,7 +625,7 @@ __global__ void __launch_bounds__(64 * BY, min_waves_per_simd<Real>()) stage_ker
     tile_y = local / d.tiles_x;
     tile_x = local - tile_y * d.tiles_x;
   }
-  stage_tile<Real, BY, WALLS>(a, tile_x * TILE_X, tile_y * (BY - 1), sm);
+  stage_tile<Real, BY, WALLS, FN>(a, tile_x * TILE_X, tile_y * (BY - 1), sm);
 }
 
 // --------------------------------------------------------------------------
@@ -816,10 +829,15 @@ __global__ void unpack_kernel(Geometry g, const double* __restrict__ in, Real* _
 template <typename Real, int BY>
 static hipError_t stage_by(const BatchArgs& a, bool walls, int grid, hipStream_t s) {
   dim3 block(64, BY);
-  if (walls)
-    hipLaunchKernelGGL((stage_kernel<Real, BY, true>), dim3(grid), block, 0, s, a);
+  const bool fn = a.A != 0.0;
+  if (walls && fn)
+    hipLaunchKernelGGL((stage_kernel<Real, BY, true, true>), dim3(grid), block, 0, s, a);
+  else if (walls)
+    hipLaunchKernelGGL((stage_kernel<Real, BY, true, false>), dim3(grid), block, 0, s, a);
+  else if (fn)
+    hipLaunchKernelGGL((stage_kernel<Real, BY, false, true>), dim3(grid), block, 0, s, a);
   else
-    hipLaunchKernelGGL((stage_kernel<Real, BY, false>), dim3(grid), block, 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<Real, BY, false, false>), dim3(grid), block, 0, s, a);
   return hipGetLastError();
 }
 

@@ -39,7 +39,9 @@ ALG_FLOPS_PER_CELL_STAGE = 3870
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("olb_kernels.hip", "olb_consts.hpp", "olb_device.hpp", "olb_feq.hpp"):
+    # the runtime file sets the launch configuration (tile order), which the
+    # measured bytes depend on too
+    for name in ("olb_kernels.hip", "olb_runtime.hip", "olb_consts.hpp", "olb_device.hpp", "olb_feq.hpp"):
         with open(os.path.join(ROOT, "paper_1702_01690_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

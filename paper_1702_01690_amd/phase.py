@@ -45,6 +45,21 @@ def spurious(moments, tw):
     return float(np.max(np.hypot(ux, uy))), float(np.max(T - tw))
 
 
+def surface_tension(n, ds, sigma):
+    """Eq. gamma_int, sigma times the integral of (dn/dx)^2 across one
+    interface, for a half-channel profile n (specular plane before the first
+    node, wall after the last): fourth-order central differences (the profile
+    mirrored across the plane, held constant past the wall) and the
+    rectangle rule."""
+    n = np.asarray(n, dtype=np.float64).reshape(-1)
+    if n.size < 4:
+        raise ValueError("profile too short for the five-point derivative")
+    ext = np.concatenate([n[2::-1], n, np.full(3, n[-1])])
+    m = n.size
+    d = (2.0 / 3.0 * (ext[4:4 + m] - ext[2:2 + m]) - 1.0 / 12.0 * (ext[5:5 + m] - ext[1:1 + m])) / ds
+    return float(sigma * np.sum(d * d) * ds)
+
+
 def _pressure(n, T, a, b):
     return n * T / (1.0 - b * n) - a * n * n
 

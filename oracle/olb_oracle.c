@@ -343,7 +343,8 @@ int oolb_init(const oolb_params* p, oolb_ctx** out) {
   if (!p || !out) return OOLB_E_ARG;
   *out = NULL;
   if (p->nx < 1 || p->ny < 1) return OOLB_E_ARG;
-  if (p->bc_x != OOLB_BC_PERIODIC) return OOLB_E_ARG;
+  if (p->bc_x != OOLB_BC_PERIODIC && p->bc_x != OOLB_BC_SPECULAR) return OOLB_E_ARG;
+  if (p->bc_x == OOLB_BC_SPECULAR && p->nx < 3) return OOLB_E_ARG;
   if (p->bc_y != OOLB_BC_PERIODIC && p->bc_y != OOLB_BC_DIFFUSE && p->bc_y != OOLB_BC_SPECULAR_DIFFUSE)
     return OOLB_E_ARG;
   if (p->bc_y != OOLB_BC_PERIODIC && p->ny < 3) return OOLB_E_ARG;
@@ -472,11 +473,18 @@ static void moments_node(const oolb_ctx* c, const double* f, size_t i, size_t np
   *T = e / (2.0 * MASS * s0);
 }
 
-/* Distribution value at node (x, y) of population k, with periodic wrap in x,
- * and periodic wrap or wall ghost rows in y. */
+/* Distribution value at node (x, y) of population k: in x a periodic wrap,
+ * or across a specular plane (Sec. 3.4.1) the mirror node of the population
+ * with the reversed x velocity, (4 - kx, ky); then in y a periodic wrap or
+ * the wall ghost rows (so that a corner ghost is reflected twice). */
 static double fget(const oolb_ctx* c, const double* f, int k, int x, int y) {
   int nx = c->nx, ny = c->ny;
-  x = wrap(x, nx);
+  if (c->p.bc_x == OOLB_BC_SPECULAR && (x < 0 || x >= nx)) {
+    x = x < 0 ? -1 - x : 2 * nx - 1 - x;
+    k = 5 * (k / 5) + (4 - k % 5);
+  } else {
+    x = wrap(x, nx);
+  }
   if (c->p.bc_y == OOLB_BC_PERIODIC) {
     y = wrap(y, ny);
   } else if (y < 0) {
@@ -488,10 +496,13 @@ static double fget(const oolb_ctx* c, const double* f, int k, int x, int y) {
 }
 
 /* Macroscopic field at (x, y): periodic wrap, or reflection across the walls
- * (Sec. 3.4.3: n_{1-j} = n_j, Delta p_{1-j} = Delta p_j). */
+ * and specular planes (Sec. 3.4.3: n_{1-j} = n_j, Delta p_{1-j} = Delta p_j). */
 static double mget(const oolb_ctx* c, const double* g, int x, int y) {
   int nx = c->nx, ny = c->ny;
-  x = wrap(x, nx);
+  if (c->p.bc_x == OOLB_BC_SPECULAR && (x < 0 || x >= nx))
+    x = x < 0 ? -1 - x : 2 * nx - 1 - x;
+  else
+    x = wrap(x, nx);
   if (c->p.bc_y == OOLB_BC_PERIODIC) {
     y = wrap(y, ny);
   } else if (y < 0) {

@@ -34,14 +34,17 @@ enum {
 
 /* bc_y: OOLB_BC_DIFFUSE = diffuse walls at both ends of y;
  * OOLB_BC_SPECULAR_DIFFUSE = a specular symmetry plane at the low end (Sec.
- * 3.4.1) and a diffuse wall at the high end (the half channel of Sec. 5). */
-enum { OOLB_BC_PERIODIC = 0, OOLB_BC_DIFFUSE = 1, OOLB_BC_SPECULAR_DIFFUSE = 2 };
+ * 3.4.1) and a diffuse wall at the high end (the half channel of Sec. 5).
+ * bc_x: periodic, or OOLB_BC_SPECULAR = specular planes at both ends of x
+ * (Sec. 3.4.1 across x; with walls in y the corner ghosts are reflected
+ * twice, as in the Laplace test of Sec. 6). */
+enum { OOLB_BC_PERIODIC = 0, OOLB_BC_DIFFUSE = 1, OOLB_BC_SPECULAR_DIFFUSE = 2, OOLB_BC_SPECULAR = 3 };
 
 /* Problem statement (Sec. 2 and 3): lattice nx*ny of spacing ds, RK-3 step dt,
  * BGK relaxation time tau, EOS p^w = nT/(1-bn) - a n^2, surface-tension
  * parameter sigma, per-axis boundary kind, wall temperature / tangential
  * velocity of the lower (y = -ds/2) and upper (y = (ny - 1/2) ds) walls.
- * Walls are supported perpendicular to y only; bc_x must be periodic.
+ * Walls are supported perpendicular to y only; bc_x is periodic or specular.
  * precision and rho_ref exist for layout compatibility and are ignored: the
  * oracle is always FP64. */
 typedef struct oolb_params {

@@ -168,6 +168,57 @@ def test_specular_half_channel_equals_mirror_symmetric_full_channel(steps):
     assert np.all(lo == 0.0)
 
 
+def _mirror_x(fields):
+    """Periodic fields on 2 nx columns, even about x = nx - 1/2 (and, by the
+    period, about x = -1/2): n, u_y, T even, u_x odd."""
+    n, ux, uy, T = fields
+    return (np.hstack([n, n[:, ::-1]]), np.hstack([ux, -ux[:, ::-1]]), np.hstack([uy, uy[:, ::-1]]),
+            np.hstack([T, T[:, ::-1]]))
+
+
+@pytest.mark.parametrize("steps", [1, 12])
+@pytest.mark.parametrize("bc_y", [0, 2])
+def test_specular_box_equals_mirror_symmetric_periodic_domain(steps, bc_y):
+    """Sec. 3.4.1 across x: specular planes at both ends of x give the left
+    half of a periodic domain twice as wide started from fields even about
+    both planes.  With the specular plane + diffuse wall in y (the Laplace
+    test's box) the corner ghosts are the plane's reflection of the wall
+    ghosts (reflected twice at the specular-specular corner)."""
+    nx, ny, tw = 6, 9, 0.8
+    kw = dict(bc_y=bc_y, tw_lo=tw, tw_hi=tw) if bc_y else {}
+    box = oracle.Oracle(_params(nx, ny, bc_x=3, **kw))
+    wide = oracle.Oracle(_params(2 * nx, ny, **kw))
+    fields = _noisy(nx, ny, 83, n0=1.2, t0=0.9)
+    box.set_fields(*fields)
+    wide.set_fields(*_mirror_x(fields))
+    box.step(steps)
+    wide.step(steps)
+    mb, mw = box.moments(), wide.moments()
+    for a, b in zip(mb, mw):
+        np.testing.assert_allclose(a, b[:, :nx], rtol=1e-12, atol=1e-15)
+    # the wide domain stays even in n about x = nx - 1/2
+    np.testing.assert_allclose(mw[0][:, nx:], mw[0][:, :nx][:, ::-1], rtol=1e-12)
+    if bc_y:
+        np.testing.assert_allclose(box.wall_density()[1], wide.wall_density()[1][:nx], rtol=1e-12)
+
+
+def test_specular_box_conserves_mass_and_keeps_rest():
+    """Specular planes and a diffuse wall exchange no mass; the rest state at
+    T_w is a fixed point of the box."""
+    nx, ny, tw = 7, 8, 0.8
+    o = oracle.Oracle(_params(nx, ny, bc_x=3, bc_y=2, tw_lo=tw, tw_hi=tw))
+    fields = _noisy(nx, ny, 29, n0=1.1, t0=0.85)
+    o.set_fields(*fields)
+    m0 = o.moments()[0].sum()
+    o.step(15)
+    assert abs(o.moments()[0].sum() / m0 - 1.0) < 1e-13
+    o = oracle.Oracle(_params(nx, ny, bc_x=3, bc_y=2, tw_lo=tw, tw_hi=tw))
+    o.set_fields(np.full((ny, nx), 1.1), np.zeros((ny, nx)), np.zeros((ny, nx)), np.full((ny, nx), tw))
+    f0 = o.get_f()
+    o.step(6)
+    np.testing.assert_allclose(o.get_f(), f0, rtol=1e-13, atol=1e-16)
+
+
 def test_specular_half_channel_rest_state_is_a_fixed_point():
     nx, ny, tw = 3, 7, 0.75
     o = oracle.Oracle(_params(nx, ny, bc_y=2, tw_lo=tw, tw_hi=tw))

@@ -53,8 +53,13 @@ typedef enum {
 /* bc_y kinds: periodic; diffuse walls at both ends (Sec. 3.4.2); a specular
  * symmetry plane at the low end (Sec. 3.4.1: ghost rows mirror the interior
  * with p_y reversed) and a diffuse wall at the high end -- the half channel
- * of the planar-interface test (Sec. 5).  bc_x must be periodic. */
-enum { OLB_BC_PERIODIC = 0, OLB_BC_DIFFUSE = 1, OLB_BC_SPECULAR_DIFFUSE = 2 };
+ * of the planar-interface test (Sec. 5).
+ * bc_x kinds: periodic, or OLB_BC_SPECULAR: specular planes at both ends of x
+ * (Sec. 3.4.1 across x: halo columns mirror the interior with p_x reversed,
+ * the carried n and Delta p mirror too; with walls in y, corner ghosts are
+ * the mirror of the wall ghosts -- the box of the Laplace test, Sec. 6).
+ * Needs nx >= 3.  All instances of a batch share bc_x and bc_y. */
+enum { OLB_BC_PERIODIC = 0, OLB_BC_DIFFUSE = 1, OLB_BC_SPECULAR_DIFFUSE = 2, OLB_BC_SPECULAR = 3 };
 enum { OLB_FP64 = 0, OLB_FP32_MIXED = 1 };
 
 /* Problem statement of Secs. 2 and 3 of the paper:
@@ -64,9 +69,8 @@ enum { OLB_FP64 = 0, OLB_FP32_MIXED = 1 };
  *   a, b        van der Waals EOS p^w = nT/(1 - bn) - a n^2 (Eq. vdw is
  *               a = 9/8, b = 1/3).
  *   sigma       surface-tension parameter of Eq. F_def, >= 0.
- *   bc_x, bc_y  per-axis boundary kind: both ends periodic, or diffuse-
- *               reflection walls (Sec. 3.4.2).  Walls are supported across y
- *               only (bc_x must be periodic); the paper's walls across x map to
+ *   bc_x, bc_y  per-axis boundary kind (the enum above).  Walls are
+ *               supported across y only; the paper's walls across x map to
  *               this case by exchanging the axes.  Walls need ny >= 3.
  *   tw_lo/hi    wall temperature at y = -ds/2 / y = (ny - 1/2) ds.
  *   uw_lo/hi    tangential (x) wall velocity at the same walls.

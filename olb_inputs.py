@@ -74,9 +74,9 @@ class Case:
 
 
 def _params(nx, ny, ds, dt, tau, a=VDW_A, b=VDW_B, sigma=1e-4, bc_y=0,
-            tw=1.0, uw=0.0, precision=0, rho_ref=1.0):
+            tw=1.0, uw=0.0, precision=0, rho_ref=1.0, bc_x=0):
     return dict(nx=int(nx), ny=int(ny), ds=float(ds), dt=float(dt), tau=float(tau),
-                a=float(a), b=float(b), sigma=float(sigma), bc_x=0, bc_y=int(bc_y),
+                a=float(a), b=float(b), sigma=float(sigma), bc_x=int(bc_x), bc_y=int(bc_y),
                 tw_lo=float(tw), tw_hi=float(tw), uw_lo=float(uw), uw_hi=float(uw),
                 precision=int(precision), rho_ref=float(rho_ref))
 
@@ -255,6 +255,38 @@ def half_channel(nx=8, ny=40, seed=9, tw=0.8 * T_CRIT, ds=1.0 / 320, dt=2e-4, ta
     T = np.full((ny, nx), float(tw if temperature is None else temperature))
     p = _params(nx, ny, ds, dt, tau, bc_y=2, tw=tw, **kw)
     return Case(f"half{nx}x{ny}", p, n, z, z.copy(), T, 0)
+
+
+def box(nx=8, ny=12, seed=13, tw=0.8 * T_CRIT, bc_y=2, ds=1.0 / 320, dt=2e-4, tau=0.005, noise=0.01,
+        speed=0.01, temperature=None, **kw):
+    """Noisy moving vdW fluid in a box with specular planes at both ends of x
+    and, in y, the half channel's specular plane + diffuse wall (bc_y = 2),
+    diffuse walls (1) or periodic ends (0)."""
+    U = uniform(seed, 3 * nx * ny).reshape(3, ny, nx)
+    n = N_CRIT * (1.0 + noise * (2.0 * U[0] - 1.0))
+    ux = speed * (2.0 * U[1] - 1.0)
+    uy = speed * (2.0 * U[2] - 1.0)
+    T = np.full((ny, nx), float(tw if temperature is None else temperature))
+    p = _params(nx, ny, ds, dt, tau, bc_y=bc_y, tw=tw, bc_x=3, **kw)
+    return Case(f"box{nx}x{ny}y{bc_y}", p, n, ux, uy, T, 0)
+
+
+def laplace_bubble(R0, n_gas, n_liquid, sigma=5e-5, tw=0.8, N=160, ds=1.0 / 320, dt=2e-4, tau=5e-3,
+                   a=9.0 / 8.0, b=1.0 / 3.0):
+    """The Laplace test (Sec. 6): a gas bubble of radius R0 centred on the
+    corner x = y = 0 of an N x N box (specular planes at x = 0, x = N ds and
+    y = 0, a diffuse wall at T_w at y = N ds; the paper's wall is at x = 0.5
+    and its top boundary specular, the axes are exchanged here), fluid at rest
+    at T_w, the tanh profile of Eq. tanh in R = sqrt(x^2 + y^2) between the
+    given gas and liquid densities, width Eq. xiwagner."""
+    xi = np.sqrt(8.0 * sigma / (9.0 * (1.0 - tw)))
+    c = (np.arange(N) + 0.5) * ds
+    R = np.hypot(c[None, :], c[:, None])
+    n = n_gas + 0.5 * (n_liquid - n_gas) * (1.0 + np.tanh((R - R0) / xi))
+    z = np.zeros((N, N))
+    p = _params(N, N, ds, dt, tau, a=a, b=b, sigma=sigma, bc_y=2, tw=tw, bc_x=3)
+    return Case(f"laplace{R0:g}", p, n, z, z.copy(), np.full((N, N), float(tw)), 0,
+                extra={"R0": float(R0), "xi": float(xi)})
 
 
 def planar_interface(tw, n_gas, n_liquid, cells=160, ds=1.0 / 320, dt=2e-4, tau=0.005, sigma=1e-4,

@@ -68,7 +68,7 @@ struct WallBatchArgs {
 constexpr int TILE_X = 63;
 
 // One workgroup per tile of the batch's tile queue.
-hipError_t launch_stage(const BatchArgs& a, int real_bytes, int by, bool walls, hipStream_t s);
+hipError_t launch_stage(const BatchArgs& a, int real_bytes, int by, bool walls, bool xspec, hipStream_t s);
 // wall_blocks: sum over instances of ceil(nx / 64).
 hipError_t launch_walls(const WallBatchArgs& a, int real_bytes, int wall_blocks, hipStream_t s);
 // f = f^eq(n, u, T) from device fields [4][ny][nx]; also writes the carry.

@@ -257,7 +257,7 @@ constexpr int min_waves_per_simd() { return std::is_same<Real, float>::value ? O
 template <typename Real>
 constexpr int prefetch_depth() { return std::is_same<Real, float>::value ? OLB_PREFETCH32 : OLB_PREFETCH64; }
 
-template <typename Real, int BY, bool WALLS, bool FN>
+template <typename Real, int BY, bool WALLS, bool FN, bool XSPEC>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, const int y0,
                                            StageLds<Real, BY>& sm) {
   constexpr bool F32 = std::is_same<Real, float>::value;
@@ -280,13 +280,27 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   const bool active = (tx < TILE_X) && (ty < BY - 1) && (x < nx) && (y < ny);
 
   // storage offsets of this thread's tile slots (same for every population)
+  // XSPEC: specular planes at both ends of x (Sec. 3.4.1 across x): a halo
+  // column past a plane holds the mirror column of the population with the
+  // reversed x velocity (xfl), and the carried fields of the mirror column.
+  // In a wall's ghost rows this reflects the wall ghosts once more (corners).
   int soff[SLOTS], moff[SLOTS];
+  bool xfl[SLOTS];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int i = tid + s * NT;
     const int ii = i < TN ? i : TN - 1;
     const int rr = ii / TW, cc = ii - rr * TW;
-    const int gx = wrapi(x0 - 3 + cc, nx);
+    int gx;
+    xfl[s] = false;
+    if (XSPEC) {
+      const int gr = x0 - 3 + cc;
+      xfl[s] = gr < 0 || gr >= nx;
+      gx = gr < 0 ? -1 - gr : (gr >= nx ? 2 * nx - 1 - gr : gr);
+      gx = min(max(gx, 0), nx - 1);   // columns beyond the mirror band feed inactive threads only
+    } else {
+      gx = wrapi(x0 - 3 + cc, nx);
+    }
     const int gy = y0 - 3 + rr;
     int sy, my;
     if (WALLS) {
@@ -316,6 +330,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   constexpr int PF = prefetch_depth<Real>() - 1;
   static_assert(PF >= G, "the register ring must hold the next group");
   auto tile_pop = [](int t) { return t < 12 ? t : t + 1; };
+  // storage offset of population k at tile slot s (mirrored populations past
+  // specular x planes)
+  auto pl_off = [&](int k, int s) -> int64_t {
+    const int64_t o = (int64_t)k * ps + soff[s];
+    if (!XSPEC) return o;
+    return xfl[s] ? (int64_t)(5 * (k / 5) + 4 - k % 5) * ps + soff[s] : o;
+  };
   // FN: the stage has an RK base term A f^n (A != 0); a template parameter so
   // that the load counts the waits below rely on are known at compile time
   constexpr bool use_fn = FN;
@@ -340,11 +361,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
 #pragma unroll
   for (int j = 0; j < G; ++j)
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) pre0[j][s] = src[tile_pop(j) * ps + soff[s]];
+    for (int s = 0; s < SLOTS; ++s) pre0[j][s] = src[pl_off(tile_pop(j), s)];
 #pragma unroll
   for (int t = G; t < G + PF; ++t)
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[tile_pop(t) * ps + soff[s]];
+    for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[pl_off(tile_pop(t), s)];
   Real fnv[25];
 #pragma unroll
   for (int k = 0; k < 25; ++k) fnv[k] = use_fn ? fnp[k * ps + own] : (Real)0;
@@ -487,7 +508,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
         }
         if (t + PF < 24) {
 #pragma unroll
-          for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[tile_pop(t + PF) * ps + soff[s]];
+          for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[pl_off(tile_pop(t + PF), s)];
         }
       }
     }
@@ -582,7 +603,7 @@ __device__ __forceinline__ int find_instance(const InstDesc* inst, int ninst, in
 // 0): an XCD then runs vertically adjacent tiles close together in time, so
 // the halo rows they share are still in its L2 (in row order a tile's lower
 // neighbour starts about half a tile lifetime later and misses them).
-template <typename Real, int BY, bool WALLS, bool FN>
+template <typename Real, int BY, bool WALLS, bool FN, bool XSPEC>
 __global__ void __launch_bounds__(64 * BY, min_waves_per_simd<Real>()) stage_kernel(const BatchArgs ba) {
   __shared__ StageLds<Real, BY> sm;
   const int bid = blockIdx.x;
@@ -625,7 +646,7 @@ __global__ void __launch_bounds__(64 * BY, min_waves_per_simd<Real>()) stage_ker
     tile_y = local / d.tiles_x;
     tile_x = local - tile_y * d.tiles_x;
   }
-  stage_tile<Real, BY, WALLS, FN>(a, tile_x * TILE_X, tile_y * (BY - 1), sm);
+  stage_tile<Real, BY, WALLS, FN, XSPEC>(a, tile_x * TILE_X, tile_y * (BY - 1), sm);
 }
 
 // --------------------------------------------------------------------------
@@ -826,30 +847,35 @@ __global__ void unpack_kernel(Geometry g, const double* __restrict__ in, Real* _
 // launchers
 // --------------------------------------------------------------------------
 
-template <typename Real, int BY>
+template <typename Real, int BY, bool XSPEC>
 static hipError_t stage_by(const BatchArgs& a, bool walls, int grid, hipStream_t s) {
   dim3 block(64, BY);
   const bool fn = a.A != 0.0;
   if (walls && fn)
-    hipLaunchKernelGGL((stage_kernel<Real, BY, true, true>), dim3(grid), block, 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<Real, BY, true, true, XSPEC>), dim3(grid), block, 0, s, a);
   else if (walls)
-    hipLaunchKernelGGL((stage_kernel<Real, BY, true, false>), dim3(grid), block, 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<Real, BY, true, false, XSPEC>), dim3(grid), block, 0, s, a);
   else if (fn)
-    hipLaunchKernelGGL((stage_kernel<Real, BY, false, true>), dim3(grid), block, 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<Real, BY, false, true, XSPEC>), dim3(grid), block, 0, s, a);
   else
-    hipLaunchKernelGGL((stage_kernel<Real, BY, false, false>), dim3(grid), block, 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<Real, BY, false, false, XSPEC>), dim3(grid), block, 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_stage(const BatchArgs& a, int real_bytes, int by, bool walls, hipStream_t s) {
+template <typename Real, int BY>
+static hipError_t stage_x(const BatchArgs& a, bool walls, bool xspec, int grid, hipStream_t s) {
+  return xspec ? stage_by<Real, BY, true>(a, walls, grid, s) : stage_by<Real, BY, false>(a, walls, grid, s);
+}
+
+hipError_t launch_stage(const BatchArgs& a, int real_bytes, int by, bool walls, bool xspec, hipStream_t s) {
   const int grid = a.total_tiles;
   if (grid < 1) return hipErrorInvalidValue;
   if (real_bytes == 8) {
-    if (by == 16) return stage_by<double, 16>(a, walls, grid, s);
-    if (by == 8) return stage_by<double, 8>(a, walls, grid, s);
+    if (by == 16) return stage_x<double, 16>(a, walls, xspec, grid, s);
+    if (by == 8) return stage_x<double, 8>(a, walls, xspec, grid, s);
   } else {
-    if (by == 16) return stage_by<float, 16>(a, walls, grid, s);
-    if (by == 8) return stage_by<float, 8>(a, walls, grid, s);
+    if (by == 16) return stage_x<float, 16>(a, walls, xspec, grid, s);
+    if (by == 8) return stage_x<float, 8>(a, walls, xspec, grid, s);
   }
   return hipErrorInvalidValue;
 }

@@ -53,7 +53,10 @@ olb_status validate(const olb_params* p, std::string& why) {
   if (!p) { why = "null params"; return OLB_E_ARG; }
   if (p->nx < 1 || p->ny < 1) { why = "nx, ny must be >= 1"; return OLB_E_ARG; }
   if ((int64_t)(p->ny + 6) * p->nx >= (int64_t)1 << 31) { why = "lattice too large"; return OLB_E_ARG; }
-  if (p->bc_x != OLB_BC_PERIODIC) { why = "walls are supported across y only (bc_x must be periodic)"; return OLB_E_ARG; }
+  if (p->bc_x != OLB_BC_PERIODIC && p->bc_x != OLB_BC_SPECULAR) {
+    why = "bc_x must be periodic or specular (walls are supported across y only)"; return OLB_E_ARG;
+  }
+  if (p->bc_x == OLB_BC_SPECULAR && p->nx < 3) { why = "specular x planes need nx >= 3"; return OLB_E_ARG; }
   if (p->bc_y != OLB_BC_PERIODIC && p->bc_y != OLB_BC_DIFFUSE && p->bc_y != OLB_BC_SPECULAR_DIFFUSE) {
     why = "bad bc_y"; return OLB_E_ARG;
   }
@@ -88,7 +91,7 @@ olb_status validate_batch(const olb_params* p, int32_t count, std::string& why) 
       why = "instance " + std::to_string(i) + ": " + why;
       return s;
     }
-    if (p[i].precision != p[0].precision || p[i].bc_y != p[0].bc_y) {
+    if (p[i].precision != p[0].precision || p[i].bc_y != p[0].bc_y || p[i].bc_x != p[0].bc_x) {
       why = "all instances of a batch share precision and boundary kind";
       return OLB_E_ARG;
     }
@@ -109,6 +112,7 @@ struct Engine {
   int* flag = nullptr;
   int rb = 8;
   bool walls = false;
+  bool xspec = false;              // specular planes at both ends of x
   int by = 8;
   int strip = 8;                   // tile order (BatchArgs::strip)
   int cur = 0;                     // carry index of the current f^n
@@ -166,6 +170,7 @@ struct Engine {
     ws_bytes = bytes;
     rb = p[0].precision == OLB_FP32_MIXED ? 4 : 8;
     walls = p[0].bc_y != OLB_BC_PERIODIC;
+    xspec = p[0].bc_x == OLB_BC_SPECULAR;
     d_desc = (olbk::InstDesc*)ws;
     flag = (int*)(ws + align_up((size_t)n * sizeof(olbk::InstDesc)));
     size_t off = head_bytes(n);
@@ -379,7 +384,7 @@ struct Engine {
       ba.strip = strip;
       ba.A = olbc::RK_A[s];
       ba.B = olbc::RK_B[s];
-      olb_status e = hip(olbk::launch_stage(ba, rb, by, walls, stream), "stage kernel");
+      olb_status e = hip(olbk::launch_stage(ba, rb, by, walls, xspec, stream), "stage kernel");
       if (e) return e;
       cur ^= 1;
     }
@@ -467,7 +472,7 @@ struct Engine {
     long long nodes = 0;
     for (const auto& q : p) nodes += (long long)q.nx * q.ny;
     std::ostringstream k;
-    k << (rb == 8 ? "fp64" : "fp32") << (walls ? "-walls" : "-periodic") << "-n" << count()
+    k << (rb == 8 ? "fp64" : "fp32") << (walls ? "-walls" : "-periodic") << (xspec ? "-xspec" : "") << "-n" << count()
       << "-nodes" << nodes;
     return k.str();
   }

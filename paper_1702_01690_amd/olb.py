@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libolb.so")
 
 OLB_OK, OLB_E_ARG, OLB_E_CFL, OLB_E_DOMAIN, OLB_E_NONFINITE = 0, -1, -2, -3, -4
 OLB_E_WORKSPACE, OLB_E_DEVICE, OLB_E_STATE = -5, -6, -7
-OLB_BC_PERIODIC, OLB_BC_DIFFUSE, OLB_BC_SPECULAR_DIFFUSE = 0, 1, 2
+OLB_BC_PERIODIC, OLB_BC_DIFFUSE, OLB_BC_SPECULAR_DIFFUSE, OLB_BC_SPECULAR = 0, 1, 2, 3
 OLB_FP64, OLB_FP32_MIXED = 0, 1
 
 

@@ -51,7 +51,8 @@ def test_workspace_size_and_validation_codes():
     nb32 = olb.olb_workspace_bytes(_params(precision=1, rho_ref=1.0))
     assert nb32 < nb
     cases = [(dict(dt=0.02), olb.OLB_E_CFL), (dict(tau=0.0), olb.OLB_E_DOMAIN),
-             (dict(bc_x=1), olb.OLB_E_ARG), (dict(bc_y=1, ny=2), olb.OLB_E_ARG),
+             (dict(bc_x=1), olb.OLB_E_ARG), (dict(bc_x=2), olb.OLB_E_ARG), (dict(bc_x=3, nx=2), olb.OLB_E_ARG),
+             (dict(bc_y=1, ny=2), olb.OLB_E_ARG),
              (dict(nx=0), olb.OLB_E_ARG), (dict(precision=1, rho_ref=0.0), olb.OLB_E_ARG),
              (dict(bc_y=1, tw_lo=0.0), olb.OLB_E_DOMAIN), (dict(sigma=-1.0), olb.OLB_E_ARG)]
     for kw, code in cases:

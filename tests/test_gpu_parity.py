@@ -81,6 +81,10 @@ CASES = {
     "channel67x20": lambda: I.channel(67, 20, tw=0.75 * I.T_CRIT, steps=30, seed=9),
     "half40x70": lambda: I.half_channel(40, 70, seed=9, tw=0.8 * I.T_CRIT, temperature=I.T_CRIT),
     "half67x9": lambda: I.half_channel(67, 9, seed=10, tw=0.75 * I.T_CRIT, uw=0.01),
+    "box70x37": lambda: I.box(70, 37, seed=31, temperature=I.T_CRIT),
+    "box130x9": lambda: I.box(130, 9, seed=32, tw=0.75 * I.T_CRIT),
+    "box3x12": lambda: I.box(3, 12, seed=33),
+    "box40x30p": lambda: I.box(40, 30, seed=34, bc_y=0, temperature=I.T_CRIT),
 }
 
 
@@ -145,6 +149,47 @@ def test_fp64_specular_half_channel_matches_oracle(name, steps):
     assert ferr < TOL64
     assert np.all(gnw[0] == 0.0)
     assert rel_scalar(gnw[1], onw[1]) < TOL64
+
+
+@pytest.mark.parametrize("name,steps", [("box70x37", 20), ("box130x9", 30), ("box3x12", 20),
+                                        ("box40x30p", 20)])
+def test_fp64_specular_box_matches_oracle(name, steps):
+    """Specular planes at both ends of x (Sec. 3.4.1 across x) with the
+    half channel's plane + wall in y (corner ghosts reflected twice), or with
+    periodic y; ragged tiles and the narrowest box (nx = 3, every halo column
+    a mirror)."""
+    err, ferr, gnw, onw = _compare(name, steps)
+    assert max(err.values()) < TOL64, err
+    assert ferr < TOL64
+    if gnw is not None:
+        assert np.all(gnw[0] == 0.0)
+        assert rel_scalar(gnw[1], onw[1]) < TOL64
+
+
+def test_fp32_specular_box_density_within_1e5():
+    err, _, _, _ = _compare("box70x37", 10, precision=1)
+    assert err["n"] < 1e-5, err
+
+
+def test_box_equals_mirror_symmetric_periodic_domain():
+    """The GPU machine against the GPU periodic domain twice as wide started
+    from fields even about both planes (u_x odd): its left half."""
+    olb = _olb()
+    c = I.box(70, 21, seed=35, temperature=I.T_CRIT)
+    wide = dict(c.params)
+    wide.update(nx=140, bc_x=0)
+    fields = (np.hstack([c.n, c.n[:, ::-1]]), np.hstack([c.ux, -c.ux[:, ::-1]]),
+              np.hstack([c.uy, c.uy[:, ::-1]]), np.hstack([c.T, c.T[:, ::-1]]))
+    a, b = olb.Lattice(wide), olb.Lattice(c.params)
+    a.set_fields(*fields)
+    b.set_fields(*c.fields)
+    a.step(15)
+    b.step(15)
+    left = tuple(m[:, :70] for m in a.moments())
+    err = moment_errors(b.moments(), left)
+    print(f"[parity] box vs mirror-symmetric wide domain: {err}", flush=True)
+    assert max(err.values()) < TOL64, err
+    assert rel_scalar(b.wall_density()[1], a.wall_density()[1][:70]) < TOL64
 
 
 def test_fp32_specular_half_channel_density_within_1e5():

@@ -77,6 +77,9 @@ WORKLOADS = {
     "galilei": "shear waves seen from a moving frame (Sec. 6.1): ideal gas (n=1) and vdW vapour / liquid "
                "(a=9/8 b=1/3, coexistence densities at T0=0.8), N_x = 20..60 periodic, V = 0..2 step 0.1, "
                "u0=1e-3, tau=5e-4, dt=2e-4; 315 instances in one batch, 2e5 steps, amplitude every 1000 steps",
+    "laplace": "Laplace pressure test (Sec. 6): gas bubbles of R0 = 0.15..0.35 in the corner of a 160x160 FP64 "
+               "box (specular planes on three sides, diffuse wall at T_w = 0.8), a=9/8 b=1/3, ds=1/320, dt=2e-4, "
+               "tau=5e-3, sigma = 5e-5 and 1e-4; 10 instances in one batch, 4e5 steps; planar columns for gamma_pl",
     "closure": "learned closure: coarse 512x512 FP32-mixed (ds 1/80, dt 8e-4) corrected every 10 steps "
                "by the bf16 conv net, against fine 2048x2048 FP64 (ds 1/320, dt 2e-4); spinodal at "
                "T in [0.75, 0.95] T_c, n = 3.5(1 +- 1% noise), tau = 0.005; 200 coarse steps",
@@ -244,6 +247,84 @@ def run_galilei(args):
                            "launch latency, not bandwidth"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 7), "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
+def run_laplace(args):
+    """The Laplace pressure test: bubbles of five radii for two surface-
+    tension parameters in one batch; gamma_Lap from p_in - p_out against
+    1 / R_f, gamma_pl from planar interfaces of the same parameters."""
+    import torch
+    import olb_inputs as I
+    from paper_1702_01690_amd import olb, phase
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    tw, steps = 0.8, args.laplace_steps
+    ng, nl = phase.maxwell_coexistence(tw)
+    radii, sigmas = [0.15, 0.2, 0.25, 0.3, 0.35], [5e-5, 1e-4]
+    cases = [I.laplace_bubble(R, ng, nl, sigma=s, tw=tw) for s in sigmas for R in radii]
+    planar = [I.planar_interface(tw, ng, nl, sigma=s) for s in sigmas]
+    b = olb.Batch([c.params for c in cases], device="cuda:0")
+    b.use_graph(10)
+    for i, c in enumerate(cases):
+        b.set_fields(i, *c.fields)
+    q = olb.Batch([c.params for c in planar], device="cuda:0")
+    q.use_graph(10)
+    for i, c in enumerate(planar):
+        q.set_fields(i, *c.fields)
+    m0 = [float(c.n.sum()) for c in cases]
+    torch.cuda.synchronize()
+    secs, done = 0.0, 0
+    while done < steps:
+        k = min(50000, steps - done)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(b.stream)
+        b.step(k)
+        ev1.record(b.stream)
+        q.step(k)
+        b.sync()
+        q.sync()
+        secs += ev0.elapsed_time(ev1) / 1e3
+        done += k
+        log(f"{done} steps")
+    rows, table = [], {}
+    ds = cases[0].params["ds"]
+    for si, s in enumerate(sigmas):
+        rf_list, dp_list = [], []
+        for j, R0 in enumerate(radii):
+            i = si * len(radii) + j
+            n, ux, uy, T = b.moments(i)
+            xiw = cases[i].extra["xi"]
+            rf, xi, nin, nout = phase.bubble_profile(n, ds, R0, xiw)
+            pin, pout = phase.bubble_pressures(n, T, ds, rf, xi)
+            rf_list.append(rf)
+            dp_list.append(pin - pout)
+            rows.append({"sigma": s, "R0": R0, "R_f": rf, "xi_over_xi_w": xi / xiw, "n_in": nin, "n_out": nout,
+                         "p_in_minus_p_out": pin - pout, "max_u": float(np.hypot(ux, uy).max()),
+                         "mass_drift": float(n.sum() / m0[i] - 1.0)})
+        gl = phase.laplace_tension(rf_list, dp_list)
+        gp = phase.surface_tension(q.moments(si)[0], planar[si].params["ds"], s)
+        table[str(s)] = {"gamma_lap": gl, "gamma_pl": gp, "gamma_lap_over_gamma_pl_minus_1": gl / gp - 1.0}
+        log(f"sigma {s}: gamma_Lap {gl:.6e}, gamma_pl {gp:.6e}, ratio - 1 {gl / gp - 1.0:+.4f}")
+    cells = sum(c.params["nx"] * c.params["ny"] for c in cases)
+    mlups = cells * steps / secs / 1e6
+    achieved = ALG_VALUES_PER_CELL_STEP * 8 * cells * steps / secs / 1e9
+    b.close()
+    q.close()
+    out = {
+        "metric": "MLUPS per full RK3 step (D2Q25)",
+        "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(secs / steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "laplace", "description": WORKLOADS["laplace"], "nodes": cells,
+                   "instances": len(cases), "bubbles": rows, "surface_tension": table,
+                   "timed": "bubble batch stepping only (planar columns and read-outs excluded)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None},
         "cpu_baseline": None,
     }
     print(json.dumps(out))
@@ -451,6 +532,8 @@ def main():
                     help="batched workload: step the instances as separate lattices, one after another")
     ap.add_argument("--planar-steps", type=int, default=600000,
                     help="step limit of the planar-interface relaxation")
+    ap.add_argument("--laplace-steps", type=int, default=400000,
+                    help="steps of the Laplace bubbles (sigma = 1e-4 settles by ~3e5)")
     ap.add_argument("--closure-samples", type=int, default=64,
                     help="training trajectories of the closure workload (8 pairs each)")
     ap.add_argument("--closure-epochs", type=int, default=30)
@@ -476,6 +559,9 @@ def main():
         return
     if args.workload == "galilei":
         run_galilei(args)
+        return
+    if args.workload == "laplace":
+        run_laplace(args)
         return
 
     import torch

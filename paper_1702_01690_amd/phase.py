@@ -60,6 +60,46 @@ def surface_tension(n, ds, sigma):
     return float(sigma * np.sum(d * d) * ds)
 
 
+def bubble_profile(n, ds, R0, xi0):
+    """Fit of Eq. tanh in the distance R from the corner x = y = 0 to a
+    bubble's density field n[y][x] (node centres at (i + 1/2) ds): n = c +
+    h tanh((R - R_f)/xi) by least squares over every node.  Returns (R_f,
+    xi, c - h, c + h), i.e. radius, width, inner and outer densities."""
+    from scipy.optimize import curve_fit
+    n = np.asarray(n, dtype=np.float64)
+    cy = (np.arange(n.shape[0]) + 0.5) * ds
+    cx = (np.arange(n.shape[1]) + 0.5) * ds
+    R = np.hypot(cx[None, :], cy[:, None]).ravel()
+    model = lambda r, c, h, rf, xi: c + h * np.tanh((r - rf) / xi)
+    p0 = [0.5 * (n.max() + n.min()), 0.5 * (n.max() - n.min()), R0, xi0]
+    (c, h, rf, xi), _ = curve_fit(model, R, n.ravel(), p0=p0)
+    return float(rf), float(abs(xi)), float(c - h), float(c + h)
+
+
+def bubble_pressures(n, T, ds, R_f, xi, a=9.0 / 8.0, b=1.0 / 3.0, margin=5.0):
+    """Mean van der Waals pressure p^w (Eq. vdw) of the nodes inside
+    (R < R_f - margin xi) and outside (R > R_f + margin xi) a bubble centred
+    on the corner."""
+    n = np.asarray(n, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    cy = (np.arange(n.shape[0]) + 0.5) * ds
+    cx = (np.arange(n.shape[1]) + 0.5) * ds
+    R = np.hypot(cx[None, :], cy[:, None])
+    p = _pressure(n, T, a, b)
+    inner, outer = R < R_f - margin * xi, R > R_f + margin * xi
+    if not inner.any() or not outer.any():
+        raise ValueError("bubble too small or too large for the pressure regions")
+    return float(p[inner].mean()), float(p[outer].mean())
+
+
+def laplace_tension(radii, dp):
+    """Eq. Laplace, p_in - p_out = gamma / R_f, fitted through the origin
+    by least squares over several bubbles: gamma."""
+    x = 1.0 / np.asarray(radii, dtype=np.float64)
+    y = np.asarray(dp, dtype=np.float64)
+    return float(np.sum(x * y) / np.sum(x * x))
+
+
 def _pressure(n, T, a, b):
     return n * T / (1.0 - b * n) - a * n * n
 

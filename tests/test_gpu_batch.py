@@ -176,12 +176,32 @@ def test_batch_fp32_mixed_density_within_1e5():
         assert err["n"] < 1e-5, err
 
 
+def test_batch_specular_boxes_match_oracle_per_instance():
+    """Boxes with specular planes at both ends of x, of uneven sizes (one
+    narrower than a tile, one with ragged tiles, one three columns wide), in
+    one launch per stage."""
+    cases = [I.box(70, 20, seed=41, tw=0.75 * I.T_CRIT), I.box(9, 33, seed=42, temperature=I.T_CRIT),
+             I.box(3, 15, seed=43, tw=0.9 * I.T_CRIT)]
+    steps = 15
+    b = _batch(cases)
+    b.step(steps)
+    b.sync()
+    for i, c in enumerate(cases):
+        err = moment_errors(b.moments(i), _oracle_run(c, steps))
+        print(f"[batch] {c.name}: {err}", flush=True)
+        assert max(err.values()) < TOL64, (c.name, err)
+
+
 def test_batch_rejects_mixed_kinds_and_bad_index():
     olb = _olb()
     a = I.shear32().params
     w = I.channel(16, 8).params
     with pytest.raises(olb.OlbError) as e:
         olb.Batch([a, w])
+    assert e.value.code == olb.OLB_E_ARG
+    # specular x and periodic x cannot share a batch
+    with pytest.raises(olb.OlbError) as e:
+        olb.Batch([I.box(8, 12).params, I.half_channel(8, 12).params])
     assert e.value.code == olb.OLB_E_ARG
     b = olb.Batch([a])
     with pytest.raises(olb.OlbError) as e:

@@ -59,3 +59,29 @@ def test_surface_tension_of_a_tanh_profile():
     assert 10.0 < errs[0] / errs[1] < 25.0
     # a flat profile has none
     assert phase.surface_tension(np.full(50, 1.3), 0.01, 1e-4) == 0.0
+
+
+def test_bubble_profile_pressures_and_laplace_fit():
+    """The bubble analysis on a synthetic field with known answers: a tanh
+    bubble of radius 0.2 and width 0.02 in R is recovered; the pressures
+    inside and outside are those of the two uniform states (up to the tanh
+    tails); gamma is the least-squares slope of dp against 1/R through the
+    origin."""
+    from paper_1702_01690_amd import phase
+    N, ds = 160, 1.0 / 320
+    c = (np.arange(N) + 0.5) * ds
+    R = np.hypot(c[None, :], c[:, None])
+    n = 1.1 + 0.8 * np.tanh((R - 0.2) / 0.02)
+    rf, xi, nin, nout = phase.bubble_profile(n, ds, 0.22, 0.03)
+    assert abs(rf - 0.2) < 1e-10 and abs(xi - 0.02) < 1e-10
+    assert abs(nin - 0.3) < 1e-10 and abs(nout - 1.9) < 1e-10
+    T = np.full((N, N), 0.8)
+    pin, pout = phase.bubble_pressures(n, T, ds, rf, xi)
+    ref = lambda q: q * 0.8 / (1 - q / 3) - 9 / 8 * q * q
+    # the tanh tails beyond 5 xi still move n by up to 1e-4
+    assert abs(pin - ref(0.3)) < 2e-5 and abs(pout - ref(1.9)) < 2e-5
+    radii = np.array([0.15, 0.2, 0.3])
+    assert phase.laplace_tension(radii, 4.9e-3 / radii) == pytest.approx(4.9e-3, rel=1e-14)
+    noisy = 4.9e-3 / radii + np.array([1e-5, -2e-5, 1e-5])
+    x = 1 / radii
+    assert phase.laplace_tension(radii, noisy) == pytest.approx(np.dot(x, noisy) / np.dot(x, x), rel=1e-14)

@@ -76,7 +76,8 @@ WORKLOADS = {
               "in HIP graphs, relaxed to the steady state",
     "galilei": "shear waves seen from a moving frame (Sec. 6.1): ideal gas (n=1) and vdW vapour / liquid "
                "(a=9/8 b=1/3, coexistence densities at T0=0.8), N_x = 20..60 periodic, V = 0..2 step 0.1, "
-               "u0=1e-3, tau=5e-4, dt=2e-4; 315 instances in one batch, 2e5 steps, amplitude every 1000 steps",
+               "u0=1e-3, tau=5e-4, dt=2e-4; 315 instances in one batch, 2e5 steps, amplitude every 1000 steps; "
+               "then the moving bubble (Sec. 6.3, 320x160, V = 0..0.1, to t = 30)",
     "laplace": "Laplace pressure test (Sec. 6): gas bubbles of R0 = 0.15..0.35 in the corner of a 160x160 FP64 "
                "box (specular planes on three sides, diffuse wall at T_w = 0.8), a=9/8 b=1/3, ds=1/320, dt=2e-4, "
                "tau=5e-3, sigma = 5e-5 and 1e-4; 10 instances in one batch, 4e5 steps; planar columns for gamma_pl",
@@ -204,6 +205,47 @@ def run_quench(args):
     print(json.dumps(out))
 
 
+def _moving_bubble(log):
+    """Sec. 6.3: half bubbles (R0 = 0.25, sigma = 1e-4) carried with V = 0 ..
+    0.1 along the specular plane and a moving diffuse wall, to t = 30; the
+    Laplace-law surface tension against the bubble at rest and the lag of
+    the centre behind V t."""
+    import olb_inputs as I
+    from paper_1702_01690_amd import galilei as G, olb, phase
+
+    ng, nl = phase.maxwell_coexistence(0.8)
+    speeds = [0.0, 0.01, 0.02, 0.05, 0.1]
+    cases = [I.moving_bubble(V, ng, nl) for V in speeds]
+    b = olb.Batch([c.params for c in cases], device="cuda:0")
+    b.use_graph(10)
+    for i, c in enumerate(cases):
+        b.set_fields(i, *c.fields)
+    eps = {V: [] for V in speeds[1:]}
+    lag = {}
+    for s in range(1, 16):                               # t = 2, 4, ..., 30
+        b.step(10000)
+        t = 2.0 * s
+        track = []
+        for i, (V, c) in enumerate(zip(speeds, cases)):
+            n, _, _, T = b.moments(i)
+            track.append(phase.track_bubble(n, T, c.extra["x"], c.extra["y"], V * t, c.extra["R0"],
+                                            c.extra["xi"], 1.0))
+        g0 = track[0][1] * track[0][3]
+        for V, tr in zip(speeds[1:], track[1:]):
+            if t >= 20.0:
+                eps[V].append(abs(tr[1] * tr[3] / g0 - 1.0))
+            lag[V] = tr[0] - V * t
+    b.close()
+    mean = {str(V): float(np.mean(eps[V])) for V in speeds[1:]}
+    big = speeds[2:]                                     # V = 0.01 sits at the noise floor of the fit
+    out = {"mean_eps_gamma_20_30": mean, "eps_gamma_max": float(max(max(e) for e in eps.values())),
+           "exponent_b_from_V_0.02_0.1": G.order(big, [mean[str(V)] for V in big]),
+           "lag_at_t30": {str(V): lag[V] for V in speeds[1:]},
+           "lag_exponent": G.order(speeds[1:], [-lag[V] for V in speeds[1:]])}
+    log(f"moving bubble: {out}")
+    return out
+
+
 def run_galilei(args):
     """The Galilean shear-wave sweep behind the paper's two exponent tables:
     every (medium, N_x, V) run as one instance of a batch; the exponents of
@@ -229,6 +271,7 @@ def run_galilei(args):
     res = {k: (G.viscosity_ratio(a, times, u0, tau, T0), G.l2_norm(a, times, u0, tau, T0))
            for k, a in zip(keys, amps)}
     dx, vv = G.orders(res, tuple(media), sizes)
+    bubble = _moving_bubble(log)
     steps = 200 * 1000
     cells = sum(N for _, N, _ in keys)
     mlups = cells * steps / secs / 1e6
@@ -243,6 +286,7 @@ def run_galilei(args):
                    "timed": "stepping only (amplitude read-outs excluded)",
                    "dx_orders": {m: {str(V): [round(x, 6) for x in v] for V, v in dx[m].items()} for m in dx},
                    "v_orders": {m: {str(N): [round(x, 6) for x in v] for N, v in vv[m].items()} for m in vv},
+                   "moving_bubble": bubble,
                    "note": "1 x N_x lattices: a launch is one tile per instance, so the step time is "
                            "launch latency, not bandwidth"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -289,6 +289,25 @@ def laplace_bubble(R0, n_gas, n_liquid, sigma=5e-5, tw=0.8, N=160, ds=1.0 / 320,
                 extra={"R0": float(R0), "xi": float(xi)})
 
 
+def moving_bubble(V, n_gas, n_liquid, R0=0.25, sigma=1e-4, tw=0.8, N=160, ds=1.0 / 320, dt=2e-4, tau=5e-3,
+                  a=9.0 / 8.0, b=1.0 / 3.0):
+    """The moving-bubble test (Sec. 6.3): a gas bubble of radius R0 centred
+    on the specular plane at x = 0 (here y = 0), carried by a uniform
+    background velocity V parallel to the plane and to a diffuse wall at T_w
+    moving with V at y = N ds; periodic along the flow with length 2 N ds
+    (node centres x_i = (i + 1/2) ds - N ds).  Fluid at T_w, the tanh profile
+    of Eq. tanh in R with width Eq. xiwagner."""
+    xi = np.sqrt(8.0 * sigma / (9.0 * (1.0 - tw)))
+    x = (np.arange(2 * N) + 0.5) * ds - N * ds
+    y = (np.arange(N) + 0.5) * ds
+    R = np.hypot(x[None, :], y[:, None])
+    n = n_gas + 0.5 * (n_liquid - n_gas) * (1.0 + np.tanh((R - R0) / xi))
+    p = _params(2 * N, N, ds, dt, tau, a=a, b=b, sigma=sigma, bc_y=2, tw=tw, uw=V)
+    z = np.zeros((N, 2 * N))
+    return Case(f"moving_bubble_V{V:g}", p, n, np.full((N, 2 * N), float(V)), z, np.full((N, 2 * N), float(tw)),
+                0, extra={"V": float(V), "R0": float(R0), "xi": float(xi), "x": x, "y": y})
+
+
 def planar_interface(tw, n_gas, n_liquid, cells=160, ds=1.0 / 320, dt=2e-4, tau=0.005, sigma=1e-4,
                      a=9.0 / 8.0, b=1.0 / 3.0, x0=0.25):
     """The planar-interface test (Sec. 5) on the half channel: one column of

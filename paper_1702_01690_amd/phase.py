@@ -92,6 +92,38 @@ def bubble_pressures(n, T, ds, R_f, xi, a=9.0 / 8.0, b=1.0 / 3.0, margin=5.0):
     return float(p[inner].mean()), float(p[outer].mean())
 
 
+def track_bubble(n, T, x, y, xc0, R0, xi0, period, a=9.0 / 8.0, b=1.0 / 3.0, margin=5.0):
+    """A bubble centred on the plane y = 0 of a field n[y][x] periodic in x
+    with the given period: least-squares fit of Eq. tanh in the distance
+    R = sqrt(dx^2 + y^2) to the centre (x_c, 0), dx taken modulo the period;
+    then the mean p^w inside and outside (as bubble_pressures).  Returns
+    (x_c, R_f, xi, p_in - p_out); x_c is the continuation nearest xc0."""
+    from scipy.optimize import curve_fit
+    n = np.asarray(n, dtype=np.float64)
+    X, Y = np.meshgrid(np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64))
+
+    def dist(xc):
+        dx = np.mod(X - xc + 0.5 * period, period) - 0.5 * period
+        return np.hypot(dx, Y)
+
+    import warnings
+    from scipy.optimize import OptimizeWarning
+    model = lambda _, c, h, rf, xi, xc: (c + h * np.tanh((dist(xc) - rf) / xi)).ravel()
+    p0 = [0.5 * (n.max() + n.min()), 0.5 * (n.max() - n.min()), R0, xi0, xc0]
+    with warnings.catch_warnings():
+        # the covariance is not used (and is singular for a bubble at rest)
+        warnings.simplefilter("ignore", OptimizeWarning)
+        (c, h, rf, xi, xc), _ = curve_fit(model, None, n.ravel(), p0=p0)
+    xi = abs(xi)
+    xc = xc0 + (np.mod(xc - xc0 + 0.5 * period, period) - 0.5 * period)
+    R = dist(xc)
+    p = _pressure(n, np.asarray(T, dtype=np.float64), a, b)
+    inner, outer = R < rf - margin * xi, R > rf + margin * xi
+    if not inner.any() or not outer.any():
+        raise ValueError("bubble too small or too large for the pressure regions")
+    return float(xc), float(rf), float(xi), float(p[inner].mean() - p[outer].mean())
+
+
 def laplace_tension(radii, dp):
     """Eq. Laplace, p_in - p_out = gamma / R_f, fitted through the origin
     by least squares over several bubbles: gamma."""

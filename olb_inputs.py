@@ -289,6 +289,19 @@ def laplace_bubble(R0, n_gas, n_liquid, sigma=5e-5, tw=0.8, N=160, ds=1.0 / 320,
                 extra={"R0": float(R0), "xi": float(xi)})
 
 
+def sound_wave(N, V=0.0, n0=1.0, a=0.0, b=0.0, sigma=0.0, T0=0.8, tau=5e-4, dt=2e-4, du0=1e-3):
+    """A longitudinal wave seen from a moving frame (Sec. 6.2): L = 1
+    periodic in x with N nodes (one node across y), n = n0, T = T0,
+    u_x = V + du0 sin(2 pi x_i), u_y = 0, x_i = (i + 1/2)/N - 1/2."""
+    x = (np.arange(N) + 0.5) / N - 0.5
+    n = np.full((1, N), float(n0))
+    ux = (V + du0 * np.sin(2.0 * np.pi * x))[None, :]
+    uy = np.zeros((1, N))
+    T = np.full((1, N), float(T0))
+    p = _params(N, 1, 1.0 / N, dt, tau, a=a, b=b, sigma=sigma)
+    return Case(f"sound{N}_V{V:g}", p, n, ux, uy, T, 0, extra={"V": float(V), "du0": float(du0), "x": x})
+
+
 def moving_bubble(V, n_gas, n_liquid, R0=0.25, sigma=1e-4, tw=0.8, N=160, ds=1.0 / 320, dt=2e-4, tau=5e-3,
                   a=9.0 / 8.0, b=1.0 / 3.0):
     """The moving-bubble test (Sec. 6.3): a gas bubble of radius R0 centred

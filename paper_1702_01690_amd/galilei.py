@@ -1,4 +1,5 @@
-"""Galilean invariance of shear-wave damping (Sec. 6.1 of the paper).
+"""Galilean invariance of shear-wave damping (Sec. 6.1 of the paper) and of
+longitudinal waves (Sec. 6.2).
 
 A shear wave u_y = u0 sin(k x) (k = 2 pi, L = 1, periodic in x) decays as
 u0 exp(-nu_an t) with nu_an = k^2 eta_0 / rho_0 = k^2 tau T0 (Eq. shear_sol,
@@ -34,10 +35,15 @@ def amplitude(uy, x, V, t):
     return 2.0 / uy.size * float(np.sum(uy * np.sin(K * (x - V * t))))
 
 
-def sweep(cases, samples=200, every=1000, graph=10, device="cuda:0", log=None):
-    """Run the shear-wave ``cases`` (olb_inputs.shear_wave) as one batch for
-    samples * every steps.  Returns (times [samples + 1], amplitudes
-    [len(cases)][samples + 1], seconds spent stepping on the GPU)."""
+def sweep(cases, samples=200, every=1000, graph=10, device="cuda:0", log=None, component="uy"):
+    """Run the wave ``cases`` (olb_inputs.shear_wave / sound_wave) as one batch
+    for samples * every steps; the amplitude is projected from u_y (shear
+    waves) or from u_x - V (component "ux", longitudinal waves).  Returns
+    (times [samples + 1], amplitudes [len(cases)][samples + 1], seconds spent
+    stepping on the GPU)."""
+    if component not in ("uy", "ux"):
+        raise ValueError("component is 'uy' or 'ux'")
+    plane = 2 if component == "uy" else 1
     import torch
     if not torch.cuda.is_available():
         raise RuntimeError("no GPU visible: the shear-wave sweep has no CPU path")
@@ -54,8 +60,11 @@ def sweep(cases, samples=200, every=1000, graph=10, device="cuda:0", log=None):
     buf = torch.empty(int(offs[-1]), dtype=torch.float64, device=device)
     times = np.arange(samples + 1) * every * dt
     amps = np.empty((len(cases), samples + 1))
+    def wave(u, c):
+        return u if component == "uy" else u - c.extra["V"]
+
     for i, c in enumerate(cases):
-        amps[i, 0] = amplitude(c.uy, c.extra["x"], c.extra["V"], 0.0)
+        amps[i, 0] = amplitude(wave(c.uy if component == "uy" else c.ux, c), c.extra["x"], c.extra["V"], 0.0)
     secs = 0.0
     t0 = time.perf_counter()
     for s in range(1, samples + 1):
@@ -70,8 +79,8 @@ def sweep(cases, samples=200, every=1000, graph=10, device="cuda:0", log=None):
         host = buf.cpu().numpy()
         for i, c in enumerate(cases):
             n = c.params["nx"] * c.params["ny"]
-            uy = host[offs[i] + 2 * n: offs[i] + 3 * n]
-            amps[i, s] = amplitude(uy, c.extra["x"], c.extra["V"], times[s])
+            u = host[offs[i] + plane * n: offs[i] + (plane + 1) * n]
+            amps[i, s] = amplitude(wave(u, c), c.extra["x"], c.extra["V"], times[s])
         if log and s % max(samples // 10, 1) == 0:
             log(f"sample {s}/{samples} ({time.perf_counter() - t0:.1f} s)")
     batch.close()
@@ -136,3 +145,36 @@ def orders(results, media, sizes, dx_speeds=(0.0, 0.5, 1.0, 2.0), v_speeds=(0.1,
             vv[m][N] = (order(v_speeds, [results[(m, N, V)][0] - e0 for V in v_speeds]),
                         order(v_speeds, [results[(m, N, V)][1] - l0 for V in v_speeds]))
     return dx, vv
+
+
+def sound_linear(n0, T0, tau, k=K, a=0.0, b=0.0, sigma=0.0):
+    """Linearised longitudinal wave of this model (Eqs. sound_cs, long_coeff,
+    long_usol): P_eta = p^w (Eq. vdw), P_kappa = p^i = n T, eta = tau n T,
+    kappa_T = 2 tau n T (m = 1).  Returns (c_s, nu_a, nu_t, S) with S the
+    sine coefficient of Eq. long_usol for a wave started with delta n =
+    delta T = 0."""
+    dPdn = T0 / (1.0 - b * n0) ** 2 - 2.0 * a * n0
+    dPdT = n0 / (1.0 - b * n0)
+    cs2 = dPdn + (n0 * T0) / (n0 * n0) * dPdT + n0 * k * k * sigma
+    cs = float(np.sqrt(cs2))
+    eta, kap = tau * n0 * T0, 2.0 * tau * n0 * T0
+    nu_t = k * k * kap / (n0 * cs2) * (dPdn + n0 * k * k * sigma)
+    nu_a = k * k * (eta + kap) / (2.0 * n0) - 0.5 * nu_t
+    S = ((k * k * kap - n0 * nu_a) ** 2 - n0 * n0 * nu_a * nu_t) / (n0 * k * cs * (k * k * kap - n0 * (nu_a - nu_t)))
+    return cs, float(nu_a), float(nu_t), float(S)
+
+
+def sound_fit(amps, times, du0, nu0, c0, S0=None, k=K):
+    """Least-squares fit of Eq. long_usol_2, du0 e^{-nu t} [cos(c k t) +
+    S sin(c k t)], to sampled amplitudes: (nu, c, S); with S0 None the sine
+    term is dropped (the ideal-gas fit of two parameters)."""
+    from scipy.optimize import curve_fit
+    t = np.asarray(times, dtype=np.float64)
+    a = np.asarray(amps, dtype=np.float64)
+    if S0 is None:
+        f = lambda tt, nu, c: du0 * np.exp(-nu * tt) * np.cos(c * k * tt)
+        (nu, c), _ = curve_fit(f, t, a, p0=[nu0, c0], xtol=1e-15, ftol=1e-15)
+        return float(nu), float(c), 0.0
+    f = lambda tt, nu, c, S: du0 * np.exp(-nu * tt) * (np.cos(c * k * tt) + S * np.sin(c * k * tt))
+    (nu, c, S), _ = curve_fit(f, t, a, p0=[nu0, c0, S0], xtol=1e-15, ftol=1e-15)
+    return float(nu), float(c), float(S)

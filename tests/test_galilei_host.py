@@ -80,3 +80,27 @@ def test_orders_recover_planted_power_laws():
     for N in sizes:
         # the V = 0 parts cancel in the departure, leaving pure powers of V
         assert vo["ideal"][N] == pytest.approx((2.0, 1.9), abs=1e-9)
+
+
+def test_sound_linear_reduces_to_the_ideal_gas_and_matches_printed_limits():
+    """Ideal gas (a = b = sigma = 0): c_s = sqrt(2 T), nu_a = nu_t = tau k^2 T
+    (the closed forms Sec. 6.2 prints) and S = 0; the vdW liquid has the
+    oracle-independent property c_s^2 = dp/dn + T/(1 - b n) + n k^2 sigma."""
+    cs, nua, nut, S = G.sound_linear(1.0, 0.8, 5e-4)
+    assert cs == pytest.approx(np.sqrt(1.6), rel=1e-15)
+    assert nua == pytest.approx(5e-4 * (2 * np.pi) ** 2 * 0.8, rel=1e-14)
+    assert nut == pytest.approx(nua, rel=1e-14) and abs(S) < 1e-15
+    n, T, a, b, s = 1.932703, 0.8, 9 / 8, 1 / 3, 1e-4
+    cs, *_ = G.sound_linear(n, T, 5e-4, a=a, b=b, sigma=s)
+    dpdn = T / (1 - b * n) ** 2 - 2 * a * n
+    assert cs ** 2 == pytest.approx(dpdn + T / (1 - b * n) + n * (2 * np.pi) ** 2 * s, rel=1e-14)
+
+
+def test_sound_fit_recovers_a_damped_oscillation():
+    t = np.arange(501) * 0.02
+    a = 1e-3 * np.exp(-0.017 * t) * (np.cos(1.13 * 2 * np.pi * t) - 2e-4 * np.sin(1.13 * 2 * np.pi * t))
+    nu, c, S = G.sound_fit(a, t, 1e-3, 0.02, 1.1, 0.0)
+    assert nu == pytest.approx(0.017, rel=1e-9) and c == pytest.approx(1.13, rel=1e-12)
+    assert S == pytest.approx(-2e-4, rel=1e-6)
+    nu, c, S = G.sound_fit(1e-3 * np.exp(-0.02 * t) * np.cos(1.26 * 2 * np.pi * t), t, 1e-3, 0.015, 1.2)
+    assert nu == pytest.approx(0.02, rel=1e-9) and c == pytest.approx(1.26, rel=1e-12) and S == 0.0

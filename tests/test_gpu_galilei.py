@@ -160,3 +160,56 @@ def test_moving_bubble():
     assert all(lag[V] < 0.0 for V in speeds[1:])
     assert abs(lexp - 1.0) < 0.1
     b.close()
+
+
+def _sound_case(medium, N, V):
+    n0, a, b, sigma = _medium(medium)
+    return I.sound_wave(N, V, n0=n0, a=a, b=b, sigma=sigma, T0=SETUP["T0"], tau=SETUP["tau"], dt=SETUP["dt"])
+
+
+def test_moving_sound_waves_match_oracle():
+    olb = _olb()
+    cases = [_sound_case("ideal", 20, 2.0), _sound_case("vapour", 30, 0.5), _sound_case("liquid", 23, 1.3)]
+    b = olb.Batch([c.params for c in cases])
+    for i, c in enumerate(cases):
+        b.set_fields(i, *c.fields)
+    b.step(300)
+    b.sync()
+    for i, c in enumerate(cases):
+        o = oracle.Oracle(c.params)
+        o.set_fields(*c.fields)
+        o.step(300)
+        err = moment_errors(b.moments(i), o.moments())
+        print(f"[galilei] {c.name}: {err}", flush=True)
+        assert max(err.values()) < 1e-11, (c.name, err)
+    b.close()
+
+
+def test_longitudinal_waves_follow_linear_theory_in_moving_frames():
+    """Sec. 6.2: 5e4 steps sampled every 100, Eq. long_usol_2 fitted to the
+    velocity amplitude.  At N_x = 60 the damping rate is within 1e-2 of Eq.
+    long_coeff and the sound speed within 1e-5 (2e-4 at V = 2); errors fall
+    from N_x = 20 to 60; the departures of nu_a from V = 0 grow nearly as V^2
+    over 0 < V <= 0.5 (the paper's N_x = 60 exponents: 1.992, 1.973, 1.961)."""
+    _olb()
+    speeds = [0.0, 0.1, 0.2, 0.3, 0.4, 0.5, 2.0]
+    keys = [(m, N, V) for m in MEDIA for N in (20, 60) for V in speeds]
+    cases = [_sound_case(*k) for k in keys]
+    times, amps, _ = G.sweep(cases, samples=500, every=100, component="ux")
+    res = {}
+    for k, a in zip(keys, amps):
+        m = k[0]
+        n0, av, bv, sigma = _medium(m)
+        cs, nua, _, S = G.sound_linear(n0, SETUP["T0"], SETUP["tau"], a=av, b=bv, sigma=sigma)
+        nu, c, _ = G.sound_fit(a, times, 1e-3, nua, cs, None if m == "ideal" else S)
+        res[k] = (nu / nua - 1.0, c / cs - 1.0)
+    for m in MEDIA:
+        e60, e20 = res[(m, 60, 0.0)], res[(m, 20, 0.0)]
+        e2 = res[(m, 60, 2.0)]
+        vo = G.order(speeds[1:6], [res[(m, 60, V)][0] - e60[0] for V in speeds[1:6]])
+        print(f"[galilei] sound {m}: N=60 V=0 nu_a {e60[0]:+.2e} c_s {e60[1]:+.2e}; V=2 nu_a {e2[0]:+.2e} "
+              f"c_s {e2[1]:+.2e}; N=20 nu_a {e20[0]:+.2e}; V-order of nu_a {vo:.3f}", flush=True)
+        assert abs(e60[0]) < 1.2e-2 and abs(e60[1]) < 1e-5
+        assert abs(e2[0]) < 1.2e-2 and abs(e2[1]) < 2e-4
+        assert abs(e20[0]) > 5 * abs(e60[0])
+        assert abs(vo - 2.0) < 0.1

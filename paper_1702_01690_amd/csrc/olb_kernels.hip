@@ -93,29 +93,31 @@ __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, doub
   return den == 0.0 ? v2 : r;
 }
 
-// FP32: the differences are first divided by their largest magnitude (the
-// weights are scale invariant) so that the products of squared indicators stay
-// in range; an indicator product that still underflows acts as a vanishing
-// one, which changes the result by far less than FP32 rounding.
+// FP32: the weights are products of squared indicators (eighth powers of the
+// differences), which would leave the FP32 range, so each indicator is
+// scaled by 2^-2e, with 2^e bounding the largest difference magnitude m
+// (m = f 2^e, 1/2 <= f < 1).  The scaling is exact and cancels in the
+// weights; the candidate offsets stay unscaled.  An indicator that still
+// underflows acts as a vanishing one, which changes the result by far less
+// than FP32 rounding.
 __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3, float v4) {
-  float d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
+  const float d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
   const float m = fmaxf(fmaxf(fabsf(d1), fabsf(d2)), fmaxf(fabsf(d3), fabsf(d4)));
-  const float im = m > 0.0f ? frcp(m) : 0.0f;
-  d1 *= im; d2 *= im; d3 *= im; d4 *= im;
+  const int e2 = -2 * __builtin_amdgcn_frexp_expf(m);
   const float a1 = d2 - d1, b1 = __builtin_fmaf(3.0f, d2, -d1);
   const float a2 = d3 - d2, b2 = d2 + d3;
   const float a3 = d4 - d3, b3 = __builtin_fmaf(3.0f, d3, -d4);
-  const float s1 = __builtin_fmaf(a1 * (13.0f / 3.0f), a1, b1 * b1);
-  const float s2 = __builtin_fmaf(a2 * (13.0f / 3.0f), a2, b2 * b2);
-  const float s3 = __builtin_fmaf(a3 * (13.0f / 3.0f), a3, b3 * b3);
+  const float s1 = __builtin_amdgcn_ldexpf(__builtin_fmaf(a1 * (13.0f / 3.0f), a1, b1 * b1), e2);
+  const float s2 = __builtin_amdgcn_ldexpf(__builtin_fmaf(a2 * (13.0f / 3.0f), a2, b2 * b2), e2);
+  const float s3 = __builtin_amdgcn_ldexpf(__builtin_fmaf(a3 * (13.0f / 3.0f), a3, b3 * b3), e2);
   const float q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
   const float w1 = q2 * q3, w2 = 6.0f * (q1 * q3), w3 = 3.0f * (q1 * q2);
   const float e1 = __builtin_fmaf(5.0f, d2, -2.0f * d1);
-  const float e2 = __builtin_fmaf(2.0f, d3, d2);
+  const float ee2 = __builtin_fmaf(2.0f, d3, d2);
   const float e3 = __builtin_fmaf(4.0f, d3, -d4);
-  const float num = __builtin_fmaf(w1, e1, __builtin_fmaf(w2, e2, w3 * e3));
+  const float num = __builtin_fmaf(w1, e1, __builtin_fmaf(w2, ee2, w3 * e3));
   const float den = w1 + w2 + w3;
-  const float r = __builtin_fmaf(m, num * frcp(6.0f * den), v2);
+  const float r = __builtin_fmaf(num, frcp(6.0f * den), v2);
   return den == 0.0f ? v2 : r;
 }
 

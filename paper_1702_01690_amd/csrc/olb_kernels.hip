@@ -561,14 +561,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   hfac(uy, T - 1.0, hy);
   const double cfe = Bdt * a.inv_tau;
   const double dn0 = sn - a.rho0;
+  // FP32 storage: the equilibrium's departure from w rho0 (collision
+  // arithmetic, FP32 like the rest of it) from the FP64 moments; every term
+  // is small, so nothing cancels, and the FP32 factors keep the epilogue
+  // within the register budget of six waves per SIMD
+  float hxf[5], hyf[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    hxf[i] = (float)hx[i];
+    hyf[i] = (float)hy[i];
+  }
+  const float cfef = (float)cfe, dn0f = (float)dn0, rho0f = (float)a.rho0;
   double dn = 0.0, djx = 0.0, djy = 0.0, de = 0.0;
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
     const int kx = k % 5, ky = k / 5;
     Real fe;
     if (F32)
-      fe = (Real)(cfe * Wk[kx] * Wk[ky] *
-                  (dn0 * (1.0 + hx[kx]) * (1.0 + hy[ky]) + a.rho0 * (hx[kx] + hy[ky] + hx[kx] * hy[ky])));
+      fe = (Real)(cfef * ((float)(Wk[kx] * Wk[ky]) *
+                          (dn0f * (1.0f + hxf[kx]) * (1.0f + hyf[ky]) +
+                           rho0f * (hxf[kx] + hyf[ky] + hxf[kx] * hyf[ky]))));
     else
       fe = (Real)(cfe * (sn * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky]))));
     const Real out = acc[k] + fe;

@@ -214,10 +214,11 @@ __device__ __forceinline__ void carry_finish(double n, double jx, double jy, dou
 #define OLB_GROUP64 1
 #endif
 #ifndef OLB_GROUP32
-#define OLB_GROUP32 2
+#define OLB_GROUP32 1
 #endif
-// populations per LDS barrier in the stage loop: two for FP32 (+2 %), one for
-// FP64 (two cost 6 registers and 2 %)
+// populations per LDS barrier in the stage loop: one for both (FP64: two
+// cost 6 registers and 2 %; FP32: with the first group reconstructed before
+// the force, two push the stage past 80 registers and spill, -4 %)
 template <typename Real>
 constexpr int pop_group() { return std::is_same<Real, float>::value ? OLB_GROUP32 : OLB_GROUP64; }
 
@@ -229,11 +230,15 @@ struct StageLds {
   static constexpr int PB = TN * (int)sizeof(Real);
   static constexpr int MB = TN * (int)sizeof(double);
   static constexpr int G = pop_group<Real>();
-  static constexpr int BUF = (2 * G * PB > 2 * MB) ? 2 * G * PB : 2 * MB;
-  // 2G population planes, aliased with the carried (n, Delta p) tile
-  __attribute__((aligned(16))) unsigned char buf[BUF];
+  // 2G population planes
+  __attribute__((aligned(16))) Real buf[2 * G * TN];
+  // the carried (n, Delta p) tile, apart from the planes: the first group of
+  // populations is reconstructed while it is still on its way
+  __attribute__((aligned(16))) double cm[2 * TN];
   // double-buffered rows of lower-face reconstructions, one per plane buffer
   Real fy[2 * G][BY][64];
+  // x advection of the first group, parked while the force is computed
+  Real ga[G][BY][64];
 };
 
 // One 64 x BY tile (origin x0, y0) of one RK stage.
@@ -267,8 +272,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   constexpr int TN = StageLds<Real, BY>::TN;
   constexpr int NT = 64 * BY;
   constexpr int SLOTS = (TN + NT - 1) / NT;
-  Real* const pl0 = reinterpret_cast<Real*>(sm.buf);
-  double* const mn = reinterpret_cast<double*>(sm.buf);
+  Real* const pl0 = sm.buf;
+  double* const mn = sm.cm;
   double* const mp = mn + TN;
   auto& fy_sh = sm.fy;
 
@@ -342,8 +347,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   // FN: the stage has an RK base term A f^n (A != 0); a template parameter so
   // that the load counts the waits below rely on are known at compile time
   constexpr bool use_fn = FN;
-  // the carried fields first: memory reads complete in issue order, so the
-  // force stencils wait for these alone while the loads below are in flight
+  // Loads are issued before anything waits, in the order they are needed
+  // (memory reads complete in issue order): the first group of planes, the
+  // carried fields of the tile, the register ring of the next planes.  The
+  // first group is reconstructed while the carried fields are in flight; the
+  // force stencils then wait for those alone.  (Slots past the tile read a
+  // clamped, valid address.)
+  Real pre0[G][SLOTS], pre[PF][SLOTS];
+#pragma unroll
+  for (int j = 0; j < G; ++j)
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) pre0[j][s] = src[pl_off(tile_pop(j), s)];
+  __builtin_amdgcn_sched_barrier(0);
   double cn_in[SLOTS], cp_in[SLOTS];
   {
     const int64_t N = (int64_t)nx * ny;
@@ -353,37 +368,94 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       cp_in[s] = cin[N + moff[s]];
     }
   }
-  __builtin_amdgcn_sched_barrier(0);   // keep them ahead of the loads below
-  // Loads issued before anything waits: the first group of planes, the
-  // register ring behind it and this node's f^n (the RK base, folded into the
-  // accumulators below).  Their latency hides behind the force stencils
-  // instead of stalling the start of the population stream and the end of
-  // the tile.  (Slots past the tile read a clamped, valid address.)
-  Real pre0[G][SLOTS], pre[PF][SLOTS];
-#pragma unroll
-  for (int j = 0; j < G; ++j)
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) pre0[j][s] = src[pl_off(tile_pop(j), s)];
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int t = G; t < G + PF; ++t)
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[pl_off(tile_pop(t), s)];
-  Real fnv[25];
+  // population 12 (p = 0 on both axes) needs no halo: read its own value
+  const Real f12 = src[12 * ps + own];
+
+  auto plane = [&](int t) { return pl0 + (t % NB) * TN; };
 #pragma unroll
-  for (int k = 0; k < 25; ++k) fnv[k] = use_fn ? fnp[k * ps + own] : (Real)0;
-  // carried n and Delta p of f_src, tile + halo, into LDS
-  {
+  for (int j = 0; j < G; ++j)
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int i = tid + s * NT;
-      if (i < TN) {
-        mn[i] = cn_in[s];
-        mp[i] = cp_in[s];
-      }
+      if (i < TN) plane(j)[i] = pre0[j][s];
+    }
+  __syncthreads();
+
+  const int rowc = (ty + 3) * TW + tx;   // x-face row values start here
+  const int colc = ty * TW + tx + 3;     // y-face column values start here
+  const int ownc = (ty + 3) * TW + tx + 3;
+
+  // WENO face reconstructions of population slot t from its plane: the left
+  // x face (its right neighbour's arrives by a lane shift) and the lower y
+  // face (published in fy_sh for the wave below); returns the x advection
+  // difference, the lower-face value and the node's own value
+  auto faces = [&](int t, Real& advx, Real& ryl, Real& fk) {
+    const int k = tile_pop(t);
+    const int kx = k % 5, ky = k / 5;
+    const double px = Rk[kx], py = Rk[ky];
+    const Real* const P = plane(t);
+    fk = P[ownc];
+    Real rxl = 0;
+    ryl = 0;
+    if (kx != 2 && ty < BY - 1) {
+      const Real c0 = P[rowc], c1 = P[rowc + 1], c2 = P[rowc + 2], c3 = P[rowc + 3],
+                 c4 = P[rowc + 4], c5 = P[rowc + 5];
+      rxl = px > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
+    }
+    if (ky != 2) {
+      const Real c0 = P[colc], c1 = P[colc + TW], c2 = P[colc + 2 * TW], c3 = P[colc + 3 * TW],
+                 c4 = P[colc + 4 * TW], c5 = P[colc + 5 * TW];
+      ryl = py > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
+      fy_sh[t % NB][ty][tx] = ryl;
+    }
+    const Real rxr = (kx != 2) ? lane_next(rxl) : (Real)0;
+    advx = (kx != 2) ? (Real)px * (rxr - rxl) : (Real)0;
+  };
+
+  // the first group, before the force is known; its x advection waits in
+  // LDS and its lower faces in fy_sh (registers are short here)
+  Real fk0[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    Real advx, ryl;
+    faces(j, advx, ryl, fk0[j]);
+    sm.ga[j][ty][tx] = advx;
+  }
+  // this node's f^n now (it would crowd the registers of the reconstructions
+  // above); its latency still hides behind the force stencils
+  __builtin_amdgcn_sched_barrier(0);
+  Real fnv[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) fnv[k] = use_fn ? fnp[k * ps + own] : (Real)0;
+
+  // stage the second group and refill the ring behind it
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const int t = G + j;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int i = tid + s * NT;
+      if (i < TN) plane(t)[i] = pre[t % PF][s];
+    }
+    if (t + PF < 24) {
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[pl_off(tile_pop(t + PF), s)];
     }
   }
-  // population 12 (p = 0 on both axes) needs no halo: read its own value
-  const Real f12 = src[12 * ps + own];
+  // carried n and Delta p of f_src, tile + halo, into LDS
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int i = tid + s * NT;
+    if (i < TN) {
+      mn[i] = cn_in[s];
+      mp[i] = cp_in[s];
+    }
+  }
   __syncthreads();
 
   // force F = (1/n) grad Delta p + sigma grad lap n (Eq. F_def), 7x7 stencils
@@ -416,7 +488,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     Fx = gxs * a.inv_ds * inv_nc + a.sigma * (lxs * a.inv_ds3);
     Fy = gys * a.inv_ds * inv_nc + a.sigma * (lys * a.inv_ds3);
   }
-  // materialise the force here, before the macroscopic tile's LDS is reused
+  // materialise the force here (left alone, the compiler interleaves the
+  // stencils with the population stream and runs out of registers)
   asm volatile("" : "+v"(Fx));
   asm volatile("" : "+v"(Fy));
 
@@ -442,28 +515,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     if (use_fn) acc[k] += rA * fnv[k];
   }
 
-  __syncthreads();  // the macroscopic tile is dead; its LDS becomes the planes
-
   // The 24 planes with a halo (population 12 has none) stream through LDS in
   // groups of G: while group g is used from buffers (t mod 2G), group g + 1 is
   // written into the other G buffers and later planes are in flight into
   // registers (ring of PF slots); one barrier per group.  Per population, the
   // contributions that do not need the upper face are accumulated before the
   // barrier, the y-advection after it.
-  auto plane = [&](int t) { return pl0 + (t % NB) * TN; };
-#pragma unroll
-  for (int j = 0; j < G; ++j)
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int i = tid + s * NT;
-      if (i < TN) plane(j)[i] = pre0[j][s];
-    }
-  __syncthreads();
-
   double sn = 0.0, sjx = 0.0, sjy = 0.0, se = 0.0;   // moments of f_src
-  const int rowc = (ty + 3) * TW + tx;   // x-face row values start here
-  const int colc = ty * TW + tx + 3;     // y-face column values start here
-  const int ownc = (ty + 3) * TW + tx + 3;
   const Real tfac = cb;
 
   // everything of population k except its y-advection
@@ -495,8 +553,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     }
   };
 
+  // the first group, now that the force is known (its upper faces became
+  // visible at the barrier before the stencils)
+  {
+    Real advx[G], ryl[G];
 #pragma unroll
-  for (int t0 = 0; t0 < 24; t0 += G) {
+    for (int j = 0; j < G; ++j) {
+      local_terms(tile_pop(j), fk0[j]);
+      advx[j] = sm.ga[j][ty][tx];
+      ryl[j] = tile_pop(j) / 5 != 2 ? fy_sh[j % NB][ty][tx] : (Real)0;
+    }
+    finish_y(0, advx, ryl);
+  }
+
+#pragma unroll
+  for (int t0 = G; t0 < 24; t0 += G) {
     if (t0 == 12) local_terms(12, f12);   // population 12 keeps its place in the sums
     // stage the next group and refill the ring
 #pragma unroll
@@ -517,27 +588,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     Real advx[G], ryl[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) {
-      const int t = t0 + j, k = tile_pop(t);
-      const int kx = k % 5, ky = k / 5;
-      const double px = Rk[kx], py = Rk[ky];
-      const Real* const P = plane(t);
-      const Real fk = P[ownc];
-      Real rxl = 0;
-      ryl[j] = 0;
-      if (kx != 2 && ty < BY - 1) {
-        const Real c0 = P[rowc], c1 = P[rowc + 1], c2 = P[rowc + 2], c3 = P[rowc + 3],
-                   c4 = P[rowc + 4], c5 = P[rowc + 5];
-        rxl = px > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
-      }
-      if (ky != 2) {
-        const Real c0 = P[colc], c1 = P[colc + TW], c2 = P[colc + 2 * TW], c3 = P[colc + 3 * TW],
-                   c4 = P[colc + 4 * TW], c5 = P[colc + 5 * TW];
-        ryl[j] = py > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
-        fy_sh[t % NB][ty][tx] = ryl[j];
-      }
-      const Real rxr = (kx != 2) ? lane_next(rxl) : (Real)0;
-      advx[j] = (kx != 2) ? (Real)px * (rxr - rxl) : (Real)0;
-      local_terms(k, fk);
+      Real fk;
+      faces(t0 + j, advx[j], ryl[j], fk);
+      local_terms(tile_pop(t0 + j), fk);
     }
     __syncthreads();
     finish_y(t0, advx, ryl);

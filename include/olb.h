@@ -144,8 +144,7 @@ olb_status olb_set_tile(olb_ctx* c, int32_t by);
 /* Order in which the stage launch visits the tiles: 0 = rows of the tile
  * grid; W > 0 = vertical strips W tiles wide, visited left to right, rows
  * within a strip (tiles that run together then share halos in L2).  Default
- * 8 for FP64 (on a 2048^2 lattice it reads 25 % fewer bytes than row order),
- * 0 for FP32 storage (bound by arithmetic, not bytes).
+ * 8: on a 2048^2 FP64 lattice it reads 25 % fewer bytes than row order.
  * Results do not depend on it (bitwise).  OLB_E_ARG outside 0..1024. */
 olb_status olb_set_tile_order(olb_ctx* c, int32_t strip);
 

@@ -114,7 +114,7 @@ struct Engine {
   bool walls = false;
   bool xspec = false;              // specular planes at both ends of x
   int by = 8;
-  int strip = 8;                   // tile order (BatchArgs::strip); set per precision in init
+  int strip = 8;                   // tile order (BatchArgs::strip)
   int cur = 0;                     // carry index of the current f^n
   int total_tiles = 0, wall_blocks = 0;
   int graph_steps = 0;             // 0: direct launches
@@ -169,10 +169,6 @@ struct Engine {
     ws = (unsigned char*)workspace;
     ws_bytes = bytes;
     rb = p[0].precision == OLB_FP32_MIXED ? 4 : 8;
-    // default tile order: strips of 8 tile columns for FP64, whose stage is
-    // held back by HBM traffic that the strips cut; rows for FP32, whose
-    // stage is bound by its arithmetic (rows measured 1.4 % faster there)
-    strip = rb == 8 ? 8 : 0;
     walls = p[0].bc_y != OLB_BC_PERIODIC;
     xspec = p[0].bc_x == OLB_BC_SPECULAR;
     d_desc = (olbk::InstDesc*)ws;

@@ -192,6 +192,29 @@ def test_batch_specular_boxes_match_oracle_per_instance():
         assert max(err.values()) < TOL64, (c.name, err)
 
 
+def test_full_channels_batch_matches_oracle_on_sampled_instances():
+    """The 256-channel FP32 benchmark batch in its launch configuration
+    (one launch per stage over all channels, HIP graphs of 10 steps,
+    autotuned tile): 20 steps, then the three smallest channels against
+    their own oracle runs."""
+    cases = I.channels()
+    b = _batch(cases, graph=10)
+    b.autotune(trial_steps=2)
+    for i, c in enumerate(cases):                 # the trial overwrote the fields
+        b.set_fields(i, *c.fields)
+    steps = 20
+    b.step(steps)
+    b.sync()
+    small = sorted(range(len(cases)), key=lambda i: cases[i].params["nx"] * cases[i].params["ny"])[:3]
+    for i in small:
+        c = cases[i]
+        err = moment_errors(b.moments(i), _oracle_run(c, steps))
+        print(f"[batch] channel {i} ({c.params['nx']}x{c.params['ny']}, T_w {c.params['tw_lo']:.3f}): {err}",
+              flush=True)
+        assert err["n"] < 1e-5, (i, err)
+    b.close()
+
+
 def test_batch_rejects_mixed_kinds_and_bad_index():
     olb = _olb()
     a = I.shear32().params

@@ -252,6 +252,28 @@ def test_fp64_wave2048_full_size_equals_tiled_crop():
     assert max(err.values()) < TOL64, err
 
 
+def test_fp32_spinodal4096_full_size_equals_tiled_crop():
+    """The 4096^2 FP32 benchmark configuration (departure storage about
+    rho_ref = n_c, default tiles and order): started from a 64^2 noisy
+    spinodal field tiled 64 x 64, it stays equal to the 64^2 run tiled --
+    bitwise, every node does the same arithmetic -- while the 64^2 FP32 run
+    is checked against the oracle elsewhere."""
+    crop = I.spinodal(64, 64, steps=20)
+    full = I.spinodal(64, 64, steps=20)
+    full.params.update(nx=4096, ny=4096)
+    fields = tuple(np.tile(a, (64, 64)) for a in crop.fields)
+    full = I.Case("spinodal4096tiled", full.params, *fields, 20)
+    print("[parity] spinodal 4096^2 FP32 from a tiled 64^2 field, 20 steps", flush=True)
+    gm, _, _ = run_gpu(full, 20, precision=1, rho_ref=I.N_CRIT)
+    cm, _, _ = run_gpu(crop, 20, precision=1, rho_ref=I.N_CRIT)
+    for a, b in zip(gm, cm):
+        np.testing.assert_array_equal(a, np.tile(b, (64, 64)))
+    om, _, _ = _oracle_cached("spinodal64", 20)
+    err = moment_errors(cm, om)
+    print(f"[parity] spinodal64 FP32 crop vs oracle after 20 steps: {err}", flush=True)
+    assert err["n"] < 1e-5, err
+
+
 def test_tile_height_does_not_change_results():
     case = CASES["noisy70x37"]()
     a, fa, _ = run_gpu(case, 10, by=16)

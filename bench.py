@@ -13,6 +13,7 @@ the same workload.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -37,13 +38,21 @@ ALG_VALUES_PER_CELL_STEP = 25 * 8
 ALG_FLOPS_PER_CELL_STAGE = 3870
 
 
+def _code_only(text):
+    """Source text without comments and with whitespace collapsed: what the
+    compiler sees, so that editing a comment does not orphan a measurement."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     # the runtime file sets the launch configuration (tile order), which the
     # measured bytes depend on too
     for name in ("olb_kernels.hip", "olb_runtime.hip", "olb_consts.hpp", "olb_device.hpp", "olb_feq.hpp"):
-        with open(os.path.join(ROOT, "paper_1702_01690_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1702_01690_amd", "csrc", name), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -5,7 +5,8 @@
 //               equilibrium, force term, BGK, WENO-5 fluxes in x and y and the
 //               RK combine, plus the carried (n, Delta p) of the result for the
 //               next stage's stencils.
-// walls_kernel  diffuse-reflection ghost rows of the stage's source array.
+// walls_kernel  ghost rows of the stage's source array across y: diffuse-
+//               reflection walls, or a specular plane at the low end.
 // init / moments / carry / pack / unpack  set-up and read-out.
 //
 // Data layout: f[k][y + 3][x] (see Geometry), one cell per thread.  A 64 x BY
@@ -13,8 +14,9 @@
 // face fluxes of their neighbours, so each block writes 63 x (BY - 1) cells.
 // Per population, the tile plus a 3-node halo (69 x (BY + 5) values) is staged
 // in LDS; each thread reconstructs the WENO value on its left (x) and lower (y)
-// face only, the right face arrives from lane + 1 by a cross-lane shuffle and
-// the upper face from the next wave through LDS.
+// face only, the right face arrives from lane + 1 by a DPP wavefront shift and
+// the upper face from the next wave through LDS.  Specular planes across x
+// are folded into the halo's load addresses.
 #include <type_traits>
 
 #include "olb_consts.hpp"

@@ -418,10 +418,12 @@ def run_planar(args):
         ng, nl = phase.coexistence(m[0])
         u, dT = phase.spurious(m, t)
         gam = phase.surface_tension(m[0], cases[i].params["ds"], cases[i].params["sigma"])
+        xiw = np.sqrt(8.0 * cases[i].params["sigma"] / (9.0 * (1.0 - t)))
+        xi, _ = phase.interface_width(m[0], cases[i].params["ds"], 0.25, xiw)
         rows.append({"T_w": t, "n_g": ng, "n_l": nl,
                      "n_g_vs_maxwell": (ng - maxwell[i][0]) / maxwell[i][0],
                      "n_l_vs_maxwell": (nl - maxwell[i][1]) / maxwell[i][1],
-                     "max_u": u, "max_T_minus_Tw": dT, "gamma_pl": gam})
+                     "max_u": u, "max_T_minus_Tw": dT, "gamma_pl": gam, "xi_over_xi_w": xi / xiw})
         log(f"T_w {t}: n_g {ng:.7f} ({rows[-1]['n_g_vs_maxwell']:+.2e}), n_l {nl:.7f} "
             f"({rows[-1]['n_l_vs_maxwell']:+.2e}), |u| {u:.2e}, dT {dT:.2e}, gamma_pl {gam:.7e}")
     mlups = cells * steps / secs / 1e6

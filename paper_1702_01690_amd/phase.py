@@ -60,6 +60,19 @@ def surface_tension(n, ds, sigma):
     return float(sigma * np.sum(d * d) * ds)
 
 
+def interface_width(n, ds, x0, xi0):
+    """Fit of Eq. tanh, n = c + h tanh((x - x_i)/xi), to a half-channel
+    profile n (node centres (j + 1/2) ds from the specular plane): (xi, x_i)
+    by least squares over every node."""
+    from scipy.optimize import curve_fit
+    n = np.asarray(n, dtype=np.float64).reshape(-1)
+    x = (np.arange(n.size) + 0.5) * ds
+    model = lambda xx, c, h, xi_pos, xi: c + h * np.tanh((xx - xi_pos) / xi)
+    p0 = [0.5 * (n.max() + n.min()), 0.5 * (n.max() - n.min()), x0, xi0]
+    (c, h, xpos, xi), _ = curve_fit(model, x, n, p0=p0)
+    return float(abs(xi)), float(xpos)
+
+
 def bubble_profile(n, ds, R0, xi0):
     """Fit of Eq. tanh in the distance R from the corner x = y = 0 to a
     bubble's density field n[y][x] (node centres at (i + 1/2) ds): n = c +

@@ -99,4 +99,10 @@ def test_grid_threshold_surface_tension_and_orders():
     # gamma_pl approaches its steady value with a time constant of ~7e4 steps
     # (5.8e-6 below it after 5e5 steps)
     assert abs(gam / g["gamma_pl"]["value"][1] - 1.0) < 2e-5
+    # the fitted width of Eq. tanh sits a few % below Eq. xiwagner's (the
+    # paper: ~0.937 at sigma = 5e-5; 0.928 here at 1e-4)
+    xiw = np.sqrt(8.0 * sigma / (9.0 * (1.0 - tw)))
+    xi, xpos = phase.interface_width(b.moments(NX.index(160))[0], 1.0 / 320, 0.25, xiw)
+    print(f"[planar-grid] xi / xi_w {xi / xiw:.4f}, interface at {xpos:.5f}", flush=True)
+    assert 0.90 < xi / xiw < 0.96 and abs(xpos - 0.25) < 2e-3
     b.close()

@@ -85,3 +85,12 @@ def test_bubble_profile_pressures_and_laplace_fit():
     noisy = 4.9e-3 / radii + np.array([1e-5, -2e-5, 1e-5])
     x = 1 / radii
     assert phase.laplace_tension(radii, noisy) == pytest.approx(np.dot(x, noisy) / np.dot(x, x), rel=1e-14)
+
+
+def test_interface_width_fit_recovers_a_tanh_profile():
+    from paper_1702_01690_amd import phase
+    ds = 1.0 / 320
+    x = (np.arange(160) + 0.5) * ds
+    n = 1.09 + 0.85 * np.tanh((x - 0.2513) / 0.0197)
+    xi, xpos = phase.interface_width(n, ds, 0.25, 0.021)
+    assert xi == pytest.approx(0.0197, rel=1e-9) and xpos == pytest.approx(0.2513, rel=1e-9)

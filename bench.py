@@ -722,7 +722,7 @@ def main():
         "dtype": "f64" if precision == 0 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
-                   "nodes": cells, "instances": len(cases), "tile": f"63x{tile_by - 1}",
+                   "nodes": cells, "instances": len(cases), "tile": f"63x{tile_by}",
                    "precision": "fp64" if precision == 0 else "fp32-mixed",
                    "launch": "sequential instances" if args.sequential else "one launch per stage",
                    "wall_s": round(wall, 3)},

@@ -139,7 +139,7 @@ olb_status olb_set_f(olb_ctx* c, const double* f);
 olb_status olb_wall_density(olb_ctx* c, double* nw_lo, double* nw_hi);
 
 /* Block height of the stage kernel: 8 (default) or 16 waves per workgroup;
- * each workgroup updates 63 x (by - 1) nodes.  Results do not depend on it. */
+ * each workgroup updates 63 x by nodes.  Results do not depend on it. */
 olb_status olb_set_tile(olb_ctx* c, int32_t by);
 /* Order in which the stage launch visits the tiles: 0 = rows of the tile
  * grid; W > 0 = vertical strips W tiles wide, visited left to right, rows

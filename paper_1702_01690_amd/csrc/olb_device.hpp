@@ -41,7 +41,7 @@ struct InstDesc {
   double* nw;           // [2][nx] wall densities (lower, upper)
   double inv_ds, inv_ds3, dt, inv_tau, a, b, sigma, rho0;
   double tw[2], uw[2];  // lower / upper wall temperature and tangential velocity
-  int tiles_x, tiles_y; // stage tiles of 63 x (BY - 1) nodes
+  int tiles_x, tiles_y; // stage tiles of 63 x BY nodes
   int tile_base;        // first tile of this instance in the batch's tile queue
   int wall_block_base;  // first 64-column block of this instance (walls)
 };
@@ -64,7 +64,7 @@ struct WallBatchArgs {
 };
 
 // Tile geometry of the stage kernel: 64 lanes across x produce 63 cells, BY
-// waves across y produce BY - 1 rows.
+// waves across y produce BY rows.
 constexpr int TILE_X = 63;
 
 // One workgroup per tile of the batch's tile queue.

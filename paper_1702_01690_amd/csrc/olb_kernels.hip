@@ -10,13 +10,14 @@
 // init / moments / carry / pack / unpack  set-up and read-out.
 //
 // Data layout: f[k][y + 3][x] (see Geometry), one cell per thread.  A 64 x BY
-// thread block covers 64 x BY nodes; lane 63 and wave BY - 1 only provide the
-// face fluxes of their neighbours, so each block writes 63 x (BY - 1) cells.
-// Per population, the tile plus a 3-node halo (69 x (BY + 5) values) is staged
-// in LDS; each thread reconstructs the WENO value on its left (x) and lower (y)
-// face only, the right face arrives from lane + 1 by a DPP wavefront shift and
-// the upper face from the next wave through LDS.  Specular planes across x
-// are folded into the halo's load addresses.
+// thread block covers 64 x BY nodes; lane 63 only provides the left face of
+// its neighbour, so each block writes 63 x BY cells.  Per population, the
+// tile plus a 3-node halo (69 x (BY + 6) values) is staged in LDS; each
+// thread reconstructs the WENO value on its left (x) and lower (y) face only,
+// the right face arrives from lane + 1 by a DPP wavefront shift and the upper
+// face from the next wave through LDS.  The tile's top face is reconstructed
+// by one wave per population, in turn.  Specular planes across x are folded
+// into the halo's load addresses.
 #include <type_traits>
 
 #include "olb_consts.hpp"
@@ -227,7 +228,7 @@ constexpr int pop_group() { return std::is_same<Real, float>::value ? OLB_GROUP3
 template <typename Real, int BY>
 struct StageLds {
   static constexpr int TW = 69;          // tile columns x0-3 .. x0+65
-  static constexpr int TH = BY + 5;      // tile rows    y0-3 .. y0+BY+1
+  static constexpr int TH = BY + 6;      // tile rows    y0-3 .. y0+BY+2
   static constexpr int TN = TW * TH;
   static constexpr int PB = TN * (int)sizeof(Real);
   static constexpr int MB = TN * (int)sizeof(double);
@@ -238,7 +239,8 @@ struct StageLds {
   // populations is reconstructed while it is still on its way
   __attribute__((aligned(16))) double cm[2 * TN];
   // double-buffered rows of lower-face reconstructions, one per plane buffer
-  Real fy[2 * G][BY][64];
+  // (row BY: the tile's top face)
+  Real fy[2 * G][BY + 1][64];
   // x advection of the first group, parked while the force is computed
   Real ga[G][BY][64];
 };
@@ -248,13 +250,15 @@ struct StageLds {
 #define OLB_PREFETCH64 4
 #endif
 #ifndef OLB_PREFETCH32
-#define OLB_PREFETCH32 4
+#define OLB_PREFETCH32 3
 #endif
 // population planes in flight: plane ti is in LDS, ti + 1 .. ti + PREFETCH - 1
-// are being loaded into registers (deeper gains nothing measurable)
-// FP32 stage: ask for 6 waves per SIMD (three 8-wave workgroups per CU); the
-// register budget of 80 costs a 48-byte spill outside the population loop and
-// still runs 8 % faster than 5 waves without it.  FP64 needs ~120 registers.
+// are being loaded into registers (deeper gains nothing measurable; the FP32
+// stage, bound by its VALU issue rate, keeps one slot fewer, which frees the
+// registers it would otherwise spill)
+// FP32 stage: ask for 6 waves per SIMD (three 8-wave workgroups per CU), a
+// budget of 80 registers, 8 % faster than 5 waves.  FP64 needs ~128 registers
+// (four waves per SIMD).
 #ifndef OLB_WAVES32
 #define OLB_WAVES32 6
 #endif
@@ -286,7 +290,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   const int nx = a.g.nx, ny = a.g.ny;
   const int64_t ps = a.g.ps;
   const int x = x0 + tx, y = y0 + ty;
-  const bool active = (tx < TILE_X) && (ty < BY - 1) && (x < nx) && (y < ny);
+  const bool active = (tx < TILE_X) && (x < nx) && (y < ny);
 
   // storage offsets of this thread's tile slots (same for every population)
   // XSPEC: specular planes at both ends of x (Sec. 3.4.1 across x): a halo
@@ -401,10 +405,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     const int kx = k % 5, ky = k / 5;
     const double px = Rk[kx], py = Rk[ky];
     const Real* const P = plane(t);
+    // the tile's top face (the lower face of the row above it): wave t mod BY
+    // takes it, so the extra reconstruction is spread over the waves; first,
+    // and fenced off, so that none of this node's face values are live yet
+    if (ky != 2 && ty == t % BY) {
+      __builtin_amdgcn_sched_barrier(0);
+      const int ct = BY * TW + tx + 3;
+      const Real d0 = P[ct], d1 = P[ct + TW], d2 = P[ct + 2 * TW], d3 = P[ct + 3 * TW],
+                 d4 = P[ct + 4 * TW], d5 = P[ct + 5 * TW];
+      fy_sh[t % NB][BY][tx] = py > 0.0 ? weno_rec(d0, d1, d2, d3, d4) : weno_rec(d5, d4, d3, d2, d1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     fk = P[ownc];
     Real rxl = 0;
     ryl = 0;
-    if (kx != 2 && ty < BY - 1) {
+    if (kx != 2) {
       const Real c0 = P[rowc], c1 = P[rowc + 1], c2 = P[rowc + 2], c3 = P[rowc + 3],
                  c4 = P[rowc + 4], c5 = P[rowc + 5];
       rxl = px > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
@@ -465,9 +480,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   // keep the compiler from issuing all ~100 LDS reads at once).
   double Fx, Fy;
   {
-    const int cty = ty < BY - 1 ? ty : BY - 2;
     const int ctx = tx < TILE_X ? tx : TILE_X - 1;
-    const int c = (cty + 3) * TW + (ctx + 3);
+    const int c = (ty + 3) * TW + (ctx + 3);
     double gxs = 0.0, gys = 0.0, lxs = 0.0, lys = 0.0;
 #pragma unroll
     for (int l = 1; l <= 3; ++l) {
@@ -548,7 +562,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       const int ky = k / 5;
       Real adv = advx[j];
       if (ky != 2) {
-        const Real ryt = fy_sh[t % NB][ty < BY - 1 ? ty + 1 : ty][tx];
+        const Real ryt = fy_sh[t % NB][ty + 1][tx];
         adv += (Real)Rk[ky] * (ryt - ryl[j]);
       }
       acc[k] += cadv * adv;
@@ -715,7 +729,7 @@ __global__ void __launch_bounds__(64 * BY, min_waves_per_simd<Real>()) stage_ker
     tile_y = local / d.tiles_x;
     tile_x = local - tile_y * d.tiles_x;
   }
-  stage_tile<Real, BY, WALLS, FN, XSPEC>(a, tile_x * TILE_X, tile_y * (BY - 1), sm);
+  stage_tile<Real, BY, WALLS, FN, XSPEC>(a, tile_x * TILE_X, tile_y * BY, sm);
 }
 
 // --------------------------------------------------------------------------

@@ -147,7 +147,7 @@ struct Engine {
     for (int i = 0; i < count(); ++i) {
       olbk::InstDesc& d = desc[i];
       d.tiles_x = (p[i].nx + olbk::TILE_X - 1) / olbk::TILE_X;
-      d.tiles_y = (p[i].ny + (by - 1) - 1) / (by - 1);
+      d.tiles_y = (p[i].ny + by - 1) / by;
       d.tile_base = tiles;
       d.wall_block_base = blocks;
       tiles += d.tiles_x * d.tiles_y;

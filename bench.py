@@ -27,6 +27,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 FP64_VEC_PEAK_TFLOPS = 78.6  # MI355X vector FP64, published (FMA = 2 flops)
 FP32_VEC_PEAK_TFLOPS = 157.3
+# VALU issue: one wave64 instruction per 4 cycles per SIMD (FP64 and unpacked
+# FP32 alike), 256 CUs x 4 SIMDs at 2.4 GHz
+VALU_ISSUE_PEAK_GINST = 256 * 4 * 2.4 / 4
+# a kernel whose VALU issue time covers this much of its launch is VALU-bound
+VALU_BOUND_FRAC = 0.9
 
 # Algorithmic HBM bytes per cell per RK-3 step: 25 populations x 8 accesses
 # (stage 1: read f^n, write f1; stages 2, 3: read f_src and f^n, write).
@@ -56,9 +61,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload):
-    """Measured HBM bytes per stage launch from committed rocprofv3 counter
-    runs, if they were taken on the current kernel source."""
+def load_counters(workload):
+    """Counter figures per stage launch (HBM bytes, VALU instructions) from
+    committed rocprofv3 runs, if they were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -67,7 +72,8 @@ def load_traffic(workload):
     entry = t.get(workload)
     if not entry or entry.get("kernel_hash") != kernel_source_hash():
         return None
-    return entry.get("bytes_per_launch")
+    return entry
+
 
 
 WORKLOADS = {
@@ -690,8 +696,26 @@ def main():
     vec_peak = FP64_VEC_PEAK_TFLOPS if precision == 0 else FP32_VEC_PEAK_TFLOPS
     hbm_frac = achieved_gbs / HBM_PEAK_GBS
     alu_frac = achieved_tflops / vec_peak
-    traffic = load_traffic(args.workload) if args.precision == "auto" and not args.sequential else None
-    if alu_frac >= hbm_frac:
+    counters = load_counters(args.workload) if args.precision == "auto" and not args.sequential else None
+    traffic = counters.get("bytes_per_launch") if counters else None
+    valu = None
+    if counters and "valu" in counters:
+        v = counters["valu"]
+        issue_ginst = v["insts_per_launch"] / avg_launch_s / 1e9
+        valu = {"insts_per_launch": v["insts_per_launch"], "issue_ginst_s": round(issue_ginst, 1),
+                "issue_peak_ginst_s": VALU_ISSUE_PEAK_GINST, "issue_frac": round(issue_ginst / VALU_ISSUE_PEAK_GINST, 4),
+                "f64_tflops": round(v["f64_flops_per_launch"] / avg_launch_s / 1e12, 3),
+                "f32_tflops": round(v["f32_flops_per_launch"] / avg_launch_s / 1e12, 3),
+                "source": v["source"]}
+    if valu and valu["issue_frac"] >= VALU_BOUND_FRAC:
+        # VALU-bound: the issue rate against its peak
+        roof = {"bound": "alu", "achieved": valu["issue_ginst_s"], "peak": VALU_ISSUE_PEAK_GINST,
+                "unit": "Ginst/s (wave64 VALU)", "frac": valu["issue_frac"], "traffic": traffic,
+                "hbm": {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(hbm_frac, 4)},
+                "flops": {"achieved": round(achieved_tflops, 3), "peak": vec_peak, "unit": "TFLOP/s",
+                          "frac": round(alu_frac, 4)}}
+    elif alu_frac >= hbm_frac:
         roof = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": vec_peak,
                 "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": traffic,
                 "hbm": {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -729,6 +753,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if valu:
+        out["roofline"]["valu"] = valu
     print(json.dumps(out))
 
 

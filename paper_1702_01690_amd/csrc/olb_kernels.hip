@@ -106,7 +106,8 @@ __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, doub
 __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3, float v4) {
   const float d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
   const float m = fmaxf(fmaxf(fabsf(d1), fabsf(d2)), fmaxf(fabsf(d3), fabsf(d4)));
-  const int e2 = -2 * __builtin_amdgcn_frexp_expf(m);
+  // -2 e in one 24-bit multiply (|e| <= 150)
+  const int e2 = __mul24(__builtin_amdgcn_frexp_expf(m), -2);
   const float a1 = d2 - d1, b1 = __builtin_fmaf(3.0f, d2, -d1);
   const float a2 = d3 - d2, b2 = d2 + d3;
   const float a3 = d4 - d3, b3 = __builtin_fmaf(3.0f, d3, -d4);
@@ -114,14 +115,18 @@ __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3
   const float s2 = __builtin_amdgcn_ldexpf(__builtin_fmaf(a2 * (13.0f / 3.0f), a2, b2 * b2), e2);
   const float s3 = __builtin_amdgcn_ldexpf(__builtin_fmaf(a3 * (13.0f / 3.0f), a3, b3 * b3), e2);
   const float q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
-  const float w1 = q2 * q3, w2 = 6.0f * (q1 * q3), w3 = 3.0f * (q1 * q2);
+  // 2^-126 in the second weight keeps den > 0 without a branch: den would
+  // vanish only with two indicators zero, and then d2 = d3 = 0 (s1 = s2 = 0,
+  // s1 = s3 = 0) or d2 = d3 = d4 = 0 (s2 = s3 = 0), so e2 = 0 and the other
+  // two weights vanish: num = 0 and the result is f_i, as the rule above
+  // requires.  Elsewhere it moves den by 1e-37 at most.
+  const float w1 = q2 * q3, w2 = 6.0f * __builtin_fmaf(q1, q3, 0x1p-126f), w3 = 3.0f * (q1 * q2);
   const float e1 = __builtin_fmaf(5.0f, d2, -2.0f * d1);
   const float ee2 = __builtin_fmaf(2.0f, d3, d2);
   const float e3 = __builtin_fmaf(4.0f, d3, -d4);
   const float num = __builtin_fmaf(w1, e1, __builtin_fmaf(w2, ee2, w3 * e3));
   const float den = w1 + w2 + w3;
-  const float r = __builtin_fmaf(num, frcp(6.0f * den), v2);
-  return den == 0.0f ? v2 : r;
+  return __builtin_fmaf(num, frcp(6.0f * den), v2);
 }
 
 // Moment sums of one node: n = sum f, j = sum p f, e = sum |p|^2 f.  With the

@@ -71,7 +71,19 @@ def _noisy_vdw(nx, ny, seed=5):
                   0.02 * (2 * U[2] - 1), 1.0 + 0.02 * (2 * U[3] - 1), 20)
 
 
+def _step(nx, ny):
+    """Two density plateaus (1.0 and 1.3) with sharp steps between them,
+    fluid at rest, T = 1, vdW at the parity physics."""
+    x = np.arange(nx)
+    n = np.where((x >= nx // 4) & (x < 3 * nx // 4), 1.3, 1.0)[None, :].repeat(ny, 0)
+    p = dict(nx=nx, ny=ny, ds=1 / 64, dt=5e-4, tau=0.01, a=I.VDW_A, b=I.VDW_B, sigma=1e-4,
+             bc_x=0, bc_y=0)
+    z = np.zeros((ny, nx))
+    return I.Case(f"step{nx}x{ny}", p, n, z, z.copy(), np.ones((ny, nx)), 20)
+
+
 CASES = {
+    "step70x12": lambda: _step(70, 12),
     "shear32": lambda: I.shear32(),
     "wave64": lambda: I.wave64(),
     "spinodal64": lambda: I.spinodal(64, 64, steps=100),
@@ -377,3 +389,17 @@ def test_fp32_mixed_100_steps_within_fp32_rounding_amplification(name):
     print(f"[parity] {name} FP32-input sensitivity of the oracle: {sens}", flush=True)
     assert err["n"] < max(1e-5, 10 * sens["n"]), (err, sens)
     assert err["T"] < max(1e-5, 10 * sens["T"]), (err, sens)
+
+
+@pytest.mark.parametrize("steps", [1, 20])
+def test_density_steps_degenerate_weno_faces(steps):
+    """Faces next to an exact plateau read stencils such as (a, b, b, b, b)
+    with two vanishing indicators; the reconstruction is then the node value
+    (Tab. weno's rule).  A wrong rule there would be off by (b - a) / 3 in
+    the flux, far above either bar.  FP64 to 1e-11 (or 10x the oracle's
+    one-ulp sensitivity), FP32 storage to 1e-5 in density."""
+    err, _, _, _ = _compare("step70x12", steps)
+    tol = _tolerance("step70x12", steps)
+    assert all(err[k] < tol[k] for k in err), (err, tol)
+    err32, _, _, _ = _compare("step70x12", steps, precision=1)
+    assert err32["n"] < 1e-5, err32

@@ -605,8 +605,9 @@ def main():
         copy_kernel(args.copy_gib)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU runs are not part of it "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py: the stage kernels run on one GPU; --gpus above 1 is not supported "
+              "(the lattice would shard into y-strips with a 3-row halo exchange per stage)",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "closure":

@@ -298,7 +298,7 @@ def test_set_fields_device_matches_host_and_checks_domain():
 
 def test_trained_closure_gains_over_the_plain_coarse_run():
     """Trains the network on the GPU from 12 fine/coarse trajectories and
-    judges it on a held-out sample against the restricted fine run:
+    evaluates it on a held-out sample against the restricted fine run:
     after training on nudged pairs, per window through the solver; after one
     round of data aggregation over its own runs, along a free corrected run
     (better in the first windows, bounded later)."""

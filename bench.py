@@ -485,7 +485,7 @@ def run_closure(args):
     del samples
     log(f"trained on {info['pairs']} pairs in {t_train:.1f} s")
 
-    held = I.closure_sample(nf, seed=6000)
+    held = I.closure_sample(nf, seed=args.closure_held_seed)
     cp = I.coarse_params(held.params)
     net = olb.Closure(nf // factor, nf // factor)
     net.set_norm(*info["norm"])
@@ -598,6 +598,8 @@ def main():
     ap.add_argument("--closure-samples", type=int, default=64,
                     help="training trajectories of the closure workload (8 pairs each)")
     ap.add_argument("--closure-epochs", type=int, default=30)
+    ap.add_argument("--closure-held-seed", type=int, default=6000,
+                    help="seed of the held-out 2048^2 sample the closure is evaluated on")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a device copy of this many GiB (counter calibration)")
     args = ap.parse_args()

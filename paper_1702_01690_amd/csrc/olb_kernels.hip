@@ -412,8 +412,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     const Real* const P = plane(t);
     // the tile's top face (the lower face of the row above it): wave t mod BY
     // takes it, so the extra reconstruction is spread over the waves; first,
-    // and fenced off, so that none of this node's face values are live yet
+    // and fenced off, so that none of this node's face values are live yet.
+    // The wave doing it runs at raised issue priority until its own faces are
+    // published: the other waves of the tile wait for it at the barrier.
     if (ky != 2 && ty == t % BY) {
+      __builtin_amdgcn_s_setprio(2);
       __builtin_amdgcn_sched_barrier(0);
       const int ct = BY * TW + tx + 3;
       const Real d0 = P[ct], d1 = P[ct + TW], d2 = P[ct + 2 * TW], d3 = P[ct + 3 * TW],
@@ -435,6 +438,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       ryl = py > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
       fy_sh[t % NB][ty][tx] = ryl;
     }
+    if (ky != 2 && ty == t % BY) __builtin_amdgcn_s_setprio(0);
     const Real rxr = (kx != 2) ? lane_next(rxl) : (Real)0;
     advx = (kx != 2) ? (Real)px * (rxr - rxl) : (Real)0;
   };

@@ -50,6 +50,13 @@ def test_planar_interface_coexistence_and_spurious_currents():
     # the solver's deviation from the coexistence curve shrinks towards T_c
     errs = [abs(phase.coexistence(b.moments(i)[0])[0] / maxwell[i][0] - 1) for i in range(len(temps))]
     assert errs[0] > errs[1] > errs[2]
+    # the fitted width of Eq. tanh approaches Eq. xiwagner's towards T_c (Fig. xi)
+    ratios = []
+    for i, tw in enumerate(temps):
+        xiw = np.sqrt(8.0 * cases[i].params["sigma"] / (9.0 * (1.0 - tw)))
+        ratios.append(phase.interface_width(b.moments(i)[0], cases[i].params["ds"], 0.25, xiw)[0] / xiw)
+    print(f"[planar] xi / xi_w {np.round(ratios, 4).tolist()}", flush=True)
+    assert 0.85 < ratios[0] < ratios[1] < ratios[2] < 1.0
 
 
 def test_grid_threshold_surface_tension_and_orders():

@@ -640,28 +640,34 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   const double cfe = Bdt * a.inv_tau;
   const double dn0 = sn - a.rho0;
   // FP32 storage: the equilibrium's departure from w rho0 (collision
-  // arithmetic, FP32 like the rest of it) from the FP64 moments; every term
-  // is small, so nothing cancels, and the FP32 factors keep the epilogue
-  // within the register budget of six waves per SIMD
-  float hxf[5], hyf[5];
+  // arithmetic, FP32 like the rest of it) from the FP64 moments, in per-axis
+  // factors with w rho0 taken out exactly and every term small (nothing
+  // cancels):
+  //   cfe w_x w_y [dn0 (1 + hx)(1 + hy) + rho0 (hx + hy + hx hy)]
+  //     = [cfe w_x (dn0 + n hx)] [w_y (1 + hy)] + [cfe rho0 w_x] [w_y hy],
+  // so each population takes two FMAs on top of its accumulator.
+  float px[5], qx[5], by[5], hy_w[5];
+  {
+    const float cfef = (float)cfe, dn0f = (float)dn0, nf = (float)sn;
+    const float crf = (float)(cfe * a.rho0);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    hxf[i] = (float)hx[i];
-    hyf[i] = (float)hy[i];
+    for (int i = 0; i < 5; ++i) {
+      const float hxi = (float)hx[i], hyi = (float)hy[i], w = (float)Wk[i];
+      px[i] = (cfef * w) * __builtin_fmaf(nf, hxi, dn0f);
+      qx[i] = crf * w;
+      by[i] = __builtin_fmaf(w, hyi, w);
+      hy_w[i] = w * hyi;
+    }
   }
-  const float cfef = (float)cfe, dn0f = (float)dn0, rho0f = (float)a.rho0;
   double dn = 0.0, djx = 0.0, djy = 0.0, de = 0.0;
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
     const int kx = k % 5, ky = k / 5;
-    Real fe;
+    Real out;
     if (F32)
-      fe = (Real)(cfef * ((float)(Wk[kx] * Wk[ky]) *
-                          (dn0f * (1.0f + hxf[kx]) * (1.0f + hyf[ky]) +
-                           rho0f * (hxf[kx] + hyf[ky] + hxf[kx] * hyf[ky]))));
+      out = (Real)__builtin_fmaf(px[kx], by[ky], __builtin_fmaf(qx[kx], hy_w[ky], (float)acc[k]));
     else
-      fe = (Real)(cfe * (sn * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky]))));
-    const Real out = acc[k] + fe;
+      out = acc[k] + (Real)(cfe * (sn * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky]))));
     if (active) dst[k * ps + own] = out;
     carry_add(k, (double)out, dn, djx, djy, de);
   }

@@ -58,6 +58,9 @@ def kernel_source_hash():
     for name in ("olb_kernels.hip", "olb_runtime.hip", "olb_consts.hpp", "olb_device.hpp", "olb_feq.hpp"):
         with open(os.path.join(ROOT, "paper_1702_01690_amd", "csrc", name), encoding="utf-8") as fh:
             h.update(_code_only(fh.read()).encode())
+    # and the compiler flags the library is built with
+    from paper_1702_01690_amd import build as hip_build
+    h.update(" ".join(hip_build.FLAGS[:-2]).encode())
     return h.hexdigest()[:16]
 
 

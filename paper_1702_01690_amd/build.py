@@ -13,6 +13,10 @@ ARCH = os.environ.get("OLB_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          # packed FP32 instructions are disabled for all device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # the stage kernel's population loop must unroll fully (its accumulators
+         # are indexed by population); the default size limit left the FP32
+         # specular-x instantiations rolled, with the accumulators in scratch
+         "-mllvm", "-pragma-unroll-threshold=100000",
          "-Wall", "-Wno-unused-function",
          "-I", os.path.join(ROOT, "include")]
 

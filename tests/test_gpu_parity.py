@@ -286,10 +286,16 @@ def test_fp32_spinodal4096_full_size_equals_tiled_crop():
     assert err["n"] < 1e-5, err
 
 
-def test_tile_height_does_not_change_results():
-    case = CASES["noisy70x37"]()
-    a, fa, _ = run_gpu(case, 10, by=16)
-    b, fb, _ = run_gpu(case, 10, by=8)
+@pytest.mark.parametrize("name,precision", [("noisy70x37", 0), ("noisy70x37", 1), ("box70x37", 0),
+                                            ("box70x37", 1)])
+def test_tile_height_does_not_change_results(name, precision):
+    """63 x 16 and 63 x 8 tiles give the same bits: a face reconstructed as a
+    tile's top face equals the one the tile above reconstructs as its lower
+    face (periodic and specular-box lattices, both storage precisions)."""
+    case = CASES[name]()
+    print(f"[parity] tile height {name} precision={precision}", flush=True)
+    a, fa, _ = run_gpu(case, 10, precision=precision, by=16)
+    b, fb, _ = run_gpu(case, 10, precision=precision, by=8)
     np.testing.assert_array_equal(fa, fb)
 
 

@@ -673,6 +673,7 @@ def main():
         lat = _Sequential([olb.Lattice(c.params, device="cuda:0") for c in cases])
         for one, c in zip(lat.lats, cases):
             one.set_tile(args.tile)
+            one.set_base_temperature(float(np.mean(c.T)))   # FP32 departure base (no-op in FP64)
             one.set_fields(*c.fields)
         n_stage, n_walls = 3, 3
         tile_by = args.tile
@@ -685,12 +686,14 @@ def main():
         if args.graph:
             lat.use_graph(args.graph)
         for i, c in enumerate(cases):
+            lat.set_base_temperature(i, float(np.mean(c.T)))
             lat.set_fields(i, *c.fields)
         n_stage, n_walls = 3, 3
         tile_by = lat.tiles()[1]
     else:
         lat = olb.Lattice(cases[0].params, device="cuda:0")
         lat.set_tile(args.tile)
+        lat.set_base_temperature(float(np.mean(cases[0].T)))
         lat.set_fields(*cases[0].fields)
         n_stage, n_walls = lat.launch_counts()
         tile_by = args.tile

@@ -141,6 +141,14 @@ olb_status olb_wall_density(olb_ctx* c, double* nw_lo, double* nw_hi);
 /* Block height of the stage kernel: 8 (default) or 16 waves per workgroup;
  * each workgroup updates 63 x by nodes.  Results do not depend on it. */
 olb_status olb_set_tile(olb_ctx* c, int32_t by);
+/* FP32 departure storage keeps f - rho_ref b_kx b_ky, with the per-axis base
+ * b = w (1 + h(0, T - 1)) of the equilibrium at rest and temperature T
+ * (Eqs. feq, g_alpha; default T = 1, b = w).  A base near the state's
+ * temperature keeps the stored departures small, so that their FP32
+ * rounding stays small too.  T > 0 and finite (OLB_E_ARG otherwise); a set
+ * distribution is re-based in place (the physical state is unchanged up to
+ * FP32 rounding).  No effect on FP64 storage.  Synchronous. */
+olb_status olb_set_base_temperature(olb_ctx* c, double T);
 /* Order in which the stage launch visits the tiles: 0 = rows of the tile
  * grid; W > 0 = vertical strips W tiles wide, visited left to right, rows
  * within a strip (tiles that run together then share halos in L2).  Default
@@ -186,6 +194,8 @@ olb_status olb_batch_wall_density(olb_batch* b, int32_t i, double* nw_lo, double
  * non-default stream.  Results are bitwise those of direct launches. */
 olb_status olb_batch_use_graph(olb_batch* b, int32_t steps_per_graph);
 olb_status olb_batch_set_tile(olb_batch* b, int32_t by);
+/* olb_set_base_temperature for instance i of the batch. */
+olb_status olb_batch_set_base_temperature(olb_batch* b, int32_t i, double T);
 olb_status olb_batch_set_tile_order(olb_batch* b, int32_t strip);
 /* Choose the stage tile height (8 or 16) by timing trial_steps steps of each
  * on a uniform rest state of every instance; the choice is read from / added

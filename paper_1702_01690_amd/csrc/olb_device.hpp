@@ -30,7 +30,9 @@ struct StageArgs {
   int* flag;            // set to 1 when a non-finite density is produced
   double inv_ds, inv_ds3, dt, inv_tau, a, b, sigma;
   double A, B;          // f_dst = A f^n + B (f_src + dt L[f_src])
-  double rho0;          // FP32 departure base (f = w_k rho0 + stored value)
+  double rho0;          // FP32 departure base: f = rho0 b_kx b_ky + stored value,
+  double tref;          // b = w (1 + h(0, tref - 1)) per axis (tref = 1: b = w)
+  const float* base;    // [25] rho0 b_kx b_ky (FP32 storage), in the instance descriptor
 };
 
 // One lattice instance of a batch (device table, ascending tile_base).
@@ -39,7 +41,8 @@ struct InstDesc {
   void* f[3];           // f^n, f^(1), f^(2)
   double* carry[2];     // carried (n, Delta p), ping-pong
   double* nw;           // [2][nx] wall densities (lower, upper)
-  double inv_ds, inv_ds3, dt, inv_tau, a, b, sigma, rho0;
+  double inv_ds, inv_ds3, dt, inv_tau, a, b, sigma, rho0, tref;
+  float base[25];       // FP32 departure base per population: rho0 b_kx b_ky
   double tw[2], uw[2];  // lower / upper wall temperature and tangential velocity
   int tiles_x, tiles_y; // stage tiles of 63 x BY nodes
   int tile_base;        // first tile of this instance in the batch's tile queue
@@ -73,19 +76,19 @@ hipError_t launch_stage(const BatchArgs& a, int real_bytes, int by, bool walls, 
 hipError_t launch_walls(const WallBatchArgs& a, int real_bytes, int wall_blocks, hipStream_t s);
 // f = f^eq(n, u, T) from device fields [4][ny][nx]; also writes the carry.
 hipError_t launch_init(const Geometry& g, const double* fields, void* f, double* carry,
-                       double rho0, double a, double b, int real_bytes, hipStream_t s);
+                       double rho0, double tref, double a, double b, int real_bytes, hipStream_t s);
 // *bad = 1 if a node of device fields [4][ny][nx] is outside the domain.
 hipError_t launch_check_fields(const Geometry& g, const double* fields, double b, int* bad, hipStream_t s);
 // n, u_x, u_y, T planes [4][ny][nx] of f.
-hipError_t launch_moments(const Geometry& g, const void* f, double* out, double rho0,
+hipError_t launch_moments(const Geometry& g, const void* f, double* out, double rho0, double tref,
                           int real_bytes, hipStream_t s);
 // carried n and Delta p of f.
-hipError_t launch_carry(const Geometry& g, const void* f, double* carry, double rho0,
+hipError_t launch_carry(const Geometry& g, const void* f, double* carry, double rho0, double tref,
                         double a, double b, int real_bytes, hipStream_t s);
 // packed double [25][ny][nx] <-> stored array.
-hipError_t launch_pack(const Geometry& g, const void* f, double* out, double rho0,
+hipError_t launch_pack(const Geometry& g, const void* f, double* out, double rho0, double tref,
                        int real_bytes, hipStream_t s);
-hipError_t launch_unpack(const Geometry& g, const double* in, void* f, double rho0,
+hipError_t launch_unpack(const Geometry& g, const double* in, void* f, double rho0, double tref,
                          int real_bytes, hipStream_t s);
 
 // The stored f^n of a single-instance context, for kernels outside the stage

@@ -129,11 +129,16 @@ __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3
   return __builtin_fmaf(num, frcp(6.0f * den), v2);
 }
 
-// Moment sums of one node: n = sum f, j = sum p f, e = sum |p|^2 f.  With the
-// FP32 departure storage f = w_k rho0 + stored, and sum w = 1, sum w p = 0,
-// sum w |p|^2 = 2.
+// FP32 departure base: f = rho0 b_kx b_ky + stored value, with per-axis
+// factors b = w (1 + h0) of the equilibrium at rest and temperature tref,
+// h0 = h(0, tref - 1) (tref = 1: b = w).  Its moments: sum b = 1,
+// sum b p = 0, sum b p^2 = tref.
+__device__ __forceinline__ void base_h0(double tref, double h0[5]) { hfac(0.0, tref - 1.0, h0); }
+
+// Moment sums of one node: n = sum f, j = sum p f, e = sum |p|^2 f, with the
+// FP32 departure base added back (n: rho0, e: 2 rho0 tref).
 template <typename Real>
-__device__ __forceinline__ void sums25(const Real* f, double rho0, double& n, double& jx,
+__device__ __forceinline__ void sums25(const Real* f, double rho0, double tref, double& n, double& jx,
                                        double& jy, double& e) {
   double cs[5], rs[5];
 #pragma unroll
@@ -155,17 +160,20 @@ __device__ __forceinline__ void sums25(const Real* f, double rho0, double& n, do
   e = (R4 * R4) * ((cs[0] + cs[4]) + (rs[0] + rs[4])) + (R3 * R3) * ((cs[1] + cs[3]) + (rs[1] + rs[3]));
   if (std::is_same<Real, float>::value) {
     n += rho0;
-    e += 2.0 * rho0;
+    e += 2.0 * rho0 * tref;
   }
 }
 
-// f^eq of one node, stored form (FP64: f^eq; FP32: f^eq - w_k rho0).
+// f^eq of one node, stored form (FP64: f^eq; FP32: f^eq minus the base, as
+//   w_x w_y [dn (1 + hx)(1 + hy) + rho0 ((hx - h0x)(1 + hy) + (1 + h0x)(hy - h0y))],
+// every term small near the base state).
 template <typename Real>
-__device__ __forceinline__ void feq25(double n, double ux, double uy, double T, double rho0,
+__device__ __forceinline__ void feq25(double n, double ux, double uy, double T, double rho0, double tref,
                                       Real out[25]) {
-  double hx[5], hy[5];
+  double hx[5], hy[5], h0[5];
   hfac(ux, T - 1.0, hx);
   hfac(uy, T - 1.0, hy);
+  base_h0(tref, h0);
 #pragma unroll
   for (int ky = 0; ky < 5; ++ky)
 #pragma unroll
@@ -174,7 +182,8 @@ __device__ __forceinline__ void feq25(double n, double ux, double uy, double T, 
       if (std::is_same<Real, float>::value) {
         const double dn = n - rho0;
         out[5 * ky + kx] = (Real)(w * (dn * (1.0 + hx[kx]) * (1.0 + hy[ky]) +
-                                      rho0 * (hx[kx] + hy[ky] + hx[kx] * hy[ky])));
+                                      rho0 * ((hx[kx] - h0[kx]) * (1.0 + hy[ky]) +
+                                              (1.0 + h0[kx]) * (hy[ky] - h0[ky]))));
       } else {
         out[5 * ky + kx] = (Real)(n * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky])));
       }
@@ -202,10 +211,11 @@ __device__ __forceinline__ void carry_add(int k, double v, double& n, double& jx
 // (n, Delta p) of the carry from the running sums.
 template <bool F32>
 __device__ __forceinline__ void carry_finish(double n, double jx, double jy, double e, double rho0,
-                                             double va, double vb, double& n_out, double& dp_out) {
+                                             double tref, double va, double vb, double& n_out,
+                                             double& dp_out) {
   if (F32) {
     n += rho0;
-    e += 2.0 * rho0;
+    e += 2.0 * rho0 * tref;
   }
   const double in = 1.0 / n;
   const double vx = jx * in, vy = jy * in;
@@ -287,6 +297,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   double* const mn = sm.cm;
   double* const mp = mn + TN;
   auto& fy_sh = sm.fy;
+  const __attribute__((address_space(4))) float* const fbase =
+      (const __attribute__((address_space(4))) float*)a.base;
 
   // one wave per tile row: make the row index a scalar so that branches on
   // it are uniform
@@ -533,13 +545,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   const Real rA = (Real)a.A;
   Real acc[25];
 #pragma unroll
-  for (int k = 0; k < 25; ++k) {
-    // FP32 departure storage: M applied to the base w rho0 gives -p w rho0
-    acc[k] = F32 ? (Real)(Bdt * a.rho0 * (Fx * Rk[k % 5] + Fy * Rk[k / 5]) * Wk[k % 5] * Wk[k / 5])
-                 : (Real)0;
-    if (use_fn) acc[k] += rA * fnv[k];
-  }
-
+  for (int k = 0; k < 25; ++k) acc[k] = use_fn ? rA * fnv[k] : (Real)0;
   // The 24 planes with a halo (population 12 has none) stream through LDS in
   // groups of G: while group g is used from buffers (t mod 2G), group g + 1 is
   // written into the other G buffers and later planes are in flight into
@@ -554,7 +560,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     const int kx = k % 5, ky = k / 5;
     carry_add(k, (double)fk, sn, sjx, sjy, se);
     acc[k] += tfac * fk;
-    const Real tfx = cx * fk, tfy = cy * fk;
+    // the force term acts on the whole population: with FP32 storage the
+    // base rho0 b_kx b_ky (a uniform value, read through the scalar cache)
+    // is added back for it
+    const Real ff = F32 ? fk + (Real)fbase[k] : fk;
+    const Real tfx = cx * ff, tfy = cy * ff;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       acc[5 * ky + i] += (Real)MT.v[i][kx] * tfx;
@@ -629,7 +639,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   // moments of f_src, equilibrium (Eqs. feq, g_alpha), RK combine
   if (F32) {
     sn += a.rho0;
-    se += 2.0 * a.rho0;
+    se += 2.0 * a.rho0 * a.tref;
   }
   const double inv_n = 1.0 / sn;
   const double ux = sjx * inv_n, uy = sjy * inv_n;
@@ -643,20 +653,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   // arithmetic, FP32 like the rest of it) from the FP64 moments, in per-axis
   // factors with w rho0 taken out exactly and every term small (nothing
   // cancels):
-  //   cfe w_x w_y [dn0 (1 + hx)(1 + hy) + rho0 (hx + hy + hx hy)]
-  //     = [cfe w_x (dn0 + n hx)] [w_y (1 + hy)] + [cfe rho0 w_x] [w_y hy],
-  // so each population takes two FMAs on top of its accumulator.
+  //   cfe w_x w_y [dn0 (1 + hx)(1 + hy) + rho0 ((1 + hx)(1 + hy) - (1 + h0x)(1 + h0y))]
+  //     = [cfe w_x (dn0 (1 + hx) + rho0 (hx - h0x))] [w_y (1 + hy)]
+  //       + [cfe rho0 w_x (1 + h0x)] [w_y (hy - h0y)]
+  // (h0 = 0 for tref = 1), so each population takes two FMAs on top of its
+  // accumulator.
   float px[5], qx[5], by[5], hy_w[5];
-  {
-    const float cfef = (float)cfe, dn0f = (float)dn0, nf = (float)sn;
+  if (F32) {
+    const float cfef = (float)cfe, dn0f = (float)dn0, rho0f = (float)a.rho0;
     const float crf = (float)(cfe * a.rho0);
+    // h0 = (theta / 2) He2 + (theta^2 / 8) He4 of the base, per index
+    const double c2 = 0.5 * (a.tref - 1.0), c4 = 0.5 * c2 * c2;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-      const float hxi = (float)hx[i], hyi = (float)hy[i], w = (float)Wk[i];
-      px[i] = (cfef * w) * __builtin_fmaf(nf, hxi, dn0f);
-      qx[i] = crf * w;
-      by[i] = __builtin_fmaf(w, hyi, w);
-      hy_w[i] = w * hyi;
+      const double h0 = c2 * HE.v[2][i] + c4 * HE.v[4][i];
+      const float w = (float)Wk[i];
+      const float hxi = (float)hx[i], dxi = (float)(hx[i] - h0), dyi = (float)(hy[i] - h0);
+      px[i] = (cfef * w) * __builtin_fmaf(dn0f, 1.0f + hxi, rho0f * dxi);
+      qx[i] = crf * (float)(Wk[i] * (1.0 + h0));
+      by[i] = __builtin_fmaf(w, (float)hy[i], w);
+      hy_w[i] = w * dyi;
     }
   }
   double dn = 0.0, djx = 0.0, djy = 0.0, de = 0.0;
@@ -674,7 +690,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
 
   if (active) {
     double cn, cdp;
-    carry_finish<F32>(dn, djx, djy, de, a.rho0, a.a, a.b, cn, cdp);
+    carry_finish<F32>(dn, djx, djy, de, a.rho0, a.tref, a.a, a.b, cn, cdp);
     const int64_t N = (int64_t)nx * ny;
     const int m = y * nx + x;
     cout[m] = cn;
@@ -728,6 +744,8 @@ __global__ void __launch_bounds__(64 * BY, min_waves_per_simd<Real>()) stage_ker
   a.A = ba.A;
   a.B = ba.B;
   a.rho0 = d.rho0;
+  a.tref = d.tref;
+  a.base = d.base;
   const int local = t - d.tile_base;
   int tile_x, tile_y;
   if (ba.strip > 0 && ba.strip < d.tiles_x) {
@@ -774,10 +792,18 @@ __global__ void walls_kernel(const WallBatchArgs wa) {
   const double Tw = wall ? d.tw[1] : d.tw[0];
   const double uw = wall ? d.uw[1] : d.uw[0];
   const double rho0 = d.rho0;
+  // per-axis factors of the FP32 departure base
+  double bw[5];
+  {
+    double h0[5];
+    base_h0(d.tref, h0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) bw[i] = Wk[i] * (1.0 + h0[i]);
+  }
   if (wall == 0 && d.g.walls == 2) {
     // specular symmetry plane (Sec. 3.4.1): ghost row -1 - j of population
-    // (kx, ky) is interior row j of (kx, 4 - ky); w_k is even in p_y, so the
-    // FP32 departure values mirror the same way
+    // (kx, ky) is interior row j of (kx, 4 - ky); the FP32 departure base is
+    // even in p_y, so the departure values mirror the same way
 #pragma unroll
     for (int k = 0; k < 25; ++k) {
       const int km = 5 * (4 - k / 5) + k % 5;
@@ -813,7 +839,7 @@ __global__ void walls_kernel(const WallBatchArgs wa) {
         // face between the adjacent interior row and the first ghost row;
         // upwind order (far interior ... ghost) is the same at both walls
         double rec = (double)weno_rec(v2, v1, v0, e1, e2);
-        if (F32) rec += Wk[kx] * Wk[ky] * rho0;
+        if (F32) rec += bw[kx] * bw[ky] * rho0;
         out += Rk[ky] * rec;
       }
     }
@@ -839,7 +865,7 @@ __global__ void walls_kernel(const WallBatchArgs wa) {
     for (int kx = 0; kx < 5; ++kx) {
       const int k = 5 * ky + kx;
       double v = nw * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky]));
-      if (F32) v -= Wk[kx] * Wk[ky] * rho0;
+      if (F32) v -= bw[kx] * bw[ky] * rho0;
       Real* pk = f + k * ps + x;
       pk[g1 * nx] = (Real)v;
       pk[g2 * nx] = (Real)v;
@@ -854,13 +880,13 @@ __global__ void walls_kernel(const WallBatchArgs wa) {
 
 template <typename Real>
 __global__ void init_kernel(Geometry g, const double* __restrict__ fld, Real* __restrict__ f,
-                            double* __restrict__ carry, double rho0, double va, double vb) {
+                            double* __restrict__ carry, double rho0, double tref, double va, double vb) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= g.nx) return;
   const int64_t N = (int64_t)g.nx * g.ny;
   const int m = y * g.nx + x;
   Real fe[25];
-  feq25<Real>(fld[m], fld[N + m], fld[2 * N + m], fld[3 * N + m], rho0, fe);
+  feq25<Real>(fld[m], fld[N + m], fld[2 * N + m], fld[3 * N + m], rho0, tref, fe);
   const int own = (y + 3) * g.nx + x;
   double n = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
 #pragma unroll
@@ -868,7 +894,7 @@ __global__ void init_kernel(Geometry g, const double* __restrict__ fld, Real* __
     f[k * g.ps + own] = fe[k];
     carry_add(k, (double)fe[k], n, jx, jy, e);
   }
-  carry_finish<std::is_same<Real, float>::value>(n, jx, jy, e, rho0, va, vb, carry[m], carry[N + m]);
+  carry_finish<std::is_same<Real, float>::value>(n, jx, jy, e, rho0, tref, va, vb, carry[m], carry[N + m]);
 }
 
 template <typename Real>
@@ -880,13 +906,13 @@ __device__ __forceinline__ void load_own(const Geometry& g, const Real* f, int x
 
 template <typename Real>
 __global__ void moments_kernel(Geometry g, const Real* __restrict__ f, double* __restrict__ out,
-                               double rho0) {
+                               double rho0, double tref) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= g.nx) return;
   Real v[25];
   load_own(g, f, x, y, v);
   double n, jx, jy, e;
-  sums25<Real>(v, rho0, n, jx, jy, e);
+  sums25<Real>(v, rho0, tref, n, jx, jy, e);
   const double in = 1.0 / n, ux = jx * in, uy = jy * in;
   const int64_t N = (int64_t)g.nx * g.ny;
   const int m = y * g.nx + x;
@@ -898,7 +924,7 @@ __global__ void moments_kernel(Geometry g, const Real* __restrict__ f, double* _
 
 template <typename Real>
 __global__ void carry_kernel(Geometry g, const Real* __restrict__ f, double* __restrict__ carry,
-                             double rho0, double va, double vb) {
+                             double rho0, double tref, double va, double vb) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= g.nx) return;
   Real v[25];
@@ -908,35 +934,41 @@ __global__ void carry_kernel(Geometry g, const Real* __restrict__ f, double* __r
   for (int k = 0; k < 25; ++k) carry_add(k, (double)v[k], n, jx, jy, e);
   const int64_t N = (int64_t)g.nx * g.ny;
   const int m = y * g.nx + x;
-  carry_finish<std::is_same<Real, float>::value>(n, jx, jy, e, rho0, va, vb, carry[m], carry[N + m]);
+  carry_finish<std::is_same<Real, float>::value>(n, jx, jy, e, rho0, tref, va, vb, carry[m], carry[N + m]);
 }
 
 template <typename Real>
 __global__ void pack_kernel(Geometry g, const Real* __restrict__ f, double* __restrict__ out,
-                            double rho0) {
+                            double rho0, double tref) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= g.nx) return;
   const int64_t N = (int64_t)g.nx * g.ny;
   const int own = (y + 3) * g.nx + x, m = y * g.nx + x;
+  double h0[5];
+  base_h0(tref, h0);
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
     double v = (double)f[k * g.ps + own];
-    if (std::is_same<Real, float>::value) v += Wk[k % 5] * Wk[k / 5] * rho0;
+    if (std::is_same<Real, float>::value)
+      v += (Wk[k % 5] * (1.0 + h0[k % 5])) * (Wk[k / 5] * (1.0 + h0[k / 5])) * rho0;
     out[k * N + m] = v;
   }
 }
 
 template <typename Real>
 __global__ void unpack_kernel(Geometry g, const double* __restrict__ in, Real* __restrict__ f,
-                              double rho0) {
+                              double rho0, double tref) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= g.nx) return;
   const int64_t N = (int64_t)g.nx * g.ny;
   const int own = (y + 3) * g.nx + x, m = y * g.nx + x;
+  double h0[5];
+  base_h0(tref, h0);
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
     double v = in[k * N + m];
-    if (std::is_same<Real, float>::value) v -= Wk[k % 5] * Wk[k / 5] * rho0;
+    if (std::is_same<Real, float>::value)
+      v -= (Wk[k % 5] * (1.0 + h0[k % 5])) * (Wk[k / 5] * (1.0 + h0[k / 5])) * rho0;
     f[k * g.ps + own] = (Real)v;
   }
 }
@@ -1007,57 +1039,57 @@ hipError_t launch_check_fields(const Geometry& g, const double* fields, double b
 }
 
 hipError_t launch_init(const Geometry& g, const double* fields, void* f, double* carry,
-                       double rho0, double va, double vb, int real_bytes, hipStream_t s) {
+                       double rho0, double tref, double va, double vb, int real_bytes, hipStream_t s) {
   if (real_bytes == 8)
     hipLaunchKernelGGL(init_kernel<double>, cell_grid(g), dim3(64), 0, s, g, fields,
-                       (double*)f, carry, rho0, va, vb);
+                       (double*)f, carry, rho0, tref, va, vb);
   else
     hipLaunchKernelGGL(init_kernel<float>, cell_grid(g), dim3(64), 0, s, g, fields,
-                       (float*)f, carry, rho0, va, vb);
+                       (float*)f, carry, rho0, tref, va, vb);
   return hipGetLastError();
 }
 
-hipError_t launch_moments(const Geometry& g, const void* f, double* out, double rho0,
+hipError_t launch_moments(const Geometry& g, const void* f, double* out, double rho0, double tref,
                           int real_bytes, hipStream_t s) {
   if (real_bytes == 8)
     hipLaunchKernelGGL(moments_kernel<double>, cell_grid(g), dim3(64), 0, s, g,
-                       (const double*)f, out, rho0);
+                       (const double*)f, out, rho0, tref);
   else
     hipLaunchKernelGGL(moments_kernel<float>, cell_grid(g), dim3(64), 0, s, g,
-                       (const float*)f, out, rho0);
+                       (const float*)f, out, rho0, tref);
   return hipGetLastError();
 }
 
-hipError_t launch_carry(const Geometry& g, const void* f, double* carry, double rho0, double va,
-                        double vb, int real_bytes, hipStream_t s) {
+hipError_t launch_carry(const Geometry& g, const void* f, double* carry, double rho0, double tref,
+                        double va, double vb, int real_bytes, hipStream_t s) {
   if (real_bytes == 8)
     hipLaunchKernelGGL(carry_kernel<double>, cell_grid(g), dim3(64), 0, s, g,
-                       (const double*)f, carry, rho0, va, vb);
+                       (const double*)f, carry, rho0, tref, va, vb);
   else
     hipLaunchKernelGGL(carry_kernel<float>, cell_grid(g), dim3(64), 0, s, g,
-                       (const float*)f, carry, rho0, va, vb);
+                       (const float*)f, carry, rho0, tref, va, vb);
   return hipGetLastError();
 }
 
-hipError_t launch_pack(const Geometry& g, const void* f, double* out, double rho0,
+hipError_t launch_pack(const Geometry& g, const void* f, double* out, double rho0, double tref,
                        int real_bytes, hipStream_t s) {
   if (real_bytes == 8)
     hipLaunchKernelGGL(pack_kernel<double>, cell_grid(g), dim3(64), 0, s, g, (const double*)f,
-                       out, rho0);
+                       out, rho0, tref);
   else
     hipLaunchKernelGGL(pack_kernel<float>, cell_grid(g), dim3(64), 0, s, g, (const float*)f,
-                       out, rho0);
+                       out, rho0, tref);
   return hipGetLastError();
 }
 
-hipError_t launch_unpack(const Geometry& g, const double* in, void* f, double rho0,
+hipError_t launch_unpack(const Geometry& g, const double* in, void* f, double rho0, double tref,
                          int real_bytes, hipStream_t s) {
   if (real_bytes == 8)
     hipLaunchKernelGGL(unpack_kernel<double>, cell_grid(g), dim3(64), 0, s, g, in, (double*)f,
-                       rho0);
+                       rho0, tref);
   else
     hipLaunchKernelGGL(unpack_kernel<float>, cell_grid(g), dim3(64), 0, s, g, in, (float*)f,
-                       rho0);
+                       rho0, tref);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@
 
 #include "../../include/olb.h"
 #include "olb_consts.hpp"
+#include "olb_consts.hpp"
 #include "olb_device.hpp"
 
 namespace {
@@ -141,6 +142,15 @@ struct Engine {
     graph = nullptr;
   }
 
+  // FP32 departure base per population, rho0 b_kx b_ky with
+  // b = w (1 + (theta / 2) He2 + (theta^2 / 8) He4), theta = tref - 1
+  static void fill_base(olbk::InstDesc& d) {
+    const double c2 = 0.5 * (d.tref - 1.0), c4 = 0.5 * c2 * c2;
+    double bw[5];
+    for (int i = 0; i < 5; ++i) bw[i] = olbc::Wk[i] * (1.0 + c2 * olbc::HE.v[2][i] + c4 * olbc::HE.v[4][i]);
+    for (int k = 0; k < 25; ++k) d.base[k] = (float)(d.rho0 * bw[k % 5] * bw[k / 5]);
+  }
+
   // tile counts for the current block height, and the device table
   olb_status upload_desc() {
     int tiles = 0, blocks = 0;
@@ -195,6 +205,8 @@ struct Engine {
       d.b = p[i].b;
       d.sigma = p[i].sigma;
       d.rho0 = rho0(i);
+      d.tref = 1.0;
+      fill_base(d);
       d.tw[0] = p[i].tw_lo;
       d.tw[1] = p[i].tw_hi;
       d.uw[0] = p[i].uw_lo;
@@ -228,7 +240,7 @@ struct Engine {
   olb_status init_from_staging(int i) {
     const olbk::InstDesc& d = desc[i];
     olb_status s = hip(olbk::launch_init(d.g, (const double*)d.f[1], d.f[0], d.carry[cur], d.rho0,
-                                         d.a, d.b, rb, stream), "init kernel");
+                                         d.tref, d.a, d.b, rb, stream), "init kernel");
     if (s) return s;
     have_f[i] = true;
     return OLB_OK;
@@ -291,13 +303,36 @@ struct Engine {
     const size_t N = (size_t)p[i].nx * p[i].ny;
     s = hip(hipMemcpyAsync(d.f[1], f, 25 * N * sizeof(double), hipMemcpyHostToDevice, stream), "f upload");
     if (s) return s;
-    s = hip(olbk::launch_unpack(d.g, (const double*)d.f[1], d.f[0], d.rho0, rb, stream), "unpack kernel");
+    s = hip(olbk::launch_unpack(d.g, (const double*)d.f[1], d.f[0], d.rho0, d.tref, rb, stream), "unpack kernel");
     if (s) return s;
-    s = hip(olbk::launch_carry(d.g, d.f[0], d.carry[cur], d.rho0, d.a, d.b, rb, stream), "carry kernel");
+    s = hip(olbk::launch_carry(d.g, d.f[0], d.carry[cur], d.rho0, d.tref, d.a, d.b, rb, stream), "carry kernel");
     if (s) return s;
     s = hip(hipMemsetAsync(flag, 0, sizeof(int), stream), "flag clear");
     if (s) return s;
     have_f[i] = true;
+    return hip(hipStreamSynchronize(stream), "stream sync");
+  }
+
+  // FP32 departure base at rest and temperature T (FP64 storage ignores it).
+  // A stored state is re-based in place: packed with the old base, unpacked
+  // with the new one, its carry recomputed.
+  olb_status set_base_temperature(int i, double T) {
+    olb_status s = check_index(i);
+    if (s) return s;
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(OLB_E_ARG, "base temperature must be positive and finite");
+    olbk::InstDesc& d = desc[i];
+    if (have_f[i] && rb == 4) {
+      s = hip(olbk::launch_pack(d.g, d.f[0], (double*)d.f[1], d.rho0, d.tref, rb, stream), "pack kernel");
+      if (s) return s;
+      s = hip(olbk::launch_unpack(d.g, (const double*)d.f[1], d.f[0], d.rho0, T, rb, stream), "unpack kernel");
+      if (s) return s;
+      s = hip(olbk::launch_carry(d.g, d.f[0], d.carry[cur], d.rho0, T, d.a, d.b, rb, stream), "carry kernel");
+      if (s) return s;
+    }
+    d.tref = T;
+    fill_base(d);
+    s = upload_desc();
+    if (s) return s;
     return hip(hipStreamSynchronize(stream), "stream sync");
   }
 
@@ -318,7 +353,7 @@ struct Engine {
     if (!have_f[i]) return fail(OLB_E_STATE, "no distribution set");
     const olbk::InstDesc& d = desc[i];
     const size_t N = (size_t)p[i].nx * p[i].ny;
-    s = hip(olbk::launch_pack(d.g, d.f[0], (double*)d.f[1], d.rho0, rb, stream), "pack kernel");
+    s = hip(olbk::launch_pack(d.g, d.f[0], (double*)d.f[1], d.rho0, d.tref, rb, stream), "pack kernel");
     if (s) return s;
     s = hip(hipMemcpyAsync(f, d.f[1], 25 * N * sizeof(double), hipMemcpyDeviceToHost, stream), "f download");
     if (s) return s;
@@ -331,7 +366,7 @@ struct Engine {
     if (!out) return fail(OLB_E_ARG, "null output");
     if (!have_f[i]) return fail(OLB_E_STATE, "no distribution set");
     const olbk::InstDesc& d = desc[i];
-    return hip(olbk::launch_moments(d.g, d.f[0], out, d.rho0, rb, stream), "moments kernel");
+    return hip(olbk::launch_moments(d.g, d.f[0], out, d.rho0, d.tref, rb, stream), "moments kernel");
   }
 
   olb_status moments(int i, double* n, double* ux, double* uy, double* T) {
@@ -594,7 +629,7 @@ olb_status refresh_carry(olb_ctx* c, hipStream_t s) {
   if (!c) return OLB_E_ARG;
   Engine& e = c->e;
   const InstDesc& d = e.desc[0];
-  return e.hip(launch_carry(d.g, d.f[0], d.carry[e.cur], d.rho0, d.a, d.b, e.rb, s), "carry kernel");
+  return e.hip(launch_carry(d.g, d.f[0], d.carry[e.cur], d.rho0, d.tref, d.a, d.b, e.rb, s), "carry kernel");
 }
 }  // namespace olbk
 
@@ -663,6 +698,7 @@ olb_status olb_wall_density(olb_ctx* c, double* lo, double* hi) {
   return c ? c->e.wall_density(0, lo, hi) : OLB_E_ARG;
 }
 olb_status olb_set_tile(olb_ctx* c, int32_t by) { return c ? c->e.set_tile(by) : OLB_E_ARG; }
+olb_status olb_set_base_temperature(olb_ctx* c, double T) { return c ? c->e.set_base_temperature(0, T) : OLB_E_ARG; }
 olb_status olb_set_tile_order(olb_ctx* c, int32_t strip) { return c ? c->e.set_tile_order(strip) : OLB_E_ARG; }
 olb_status olb_launch_counts(const olb_ctx* c, int32_t* stage, int32_t* walls) {
   if (!c || !stage || !walls) return OLB_E_ARG;
@@ -732,6 +768,9 @@ olb_status olb_batch_use_graph(olb_batch* b, int32_t steps_per_graph) {
   return OLB_OK;
 }
 olb_status olb_batch_set_tile(olb_batch* b, int32_t by) { return b ? b->e.set_tile(by) : OLB_E_ARG; }
+olb_status olb_batch_set_base_temperature(olb_batch* b, int32_t i, double T) {
+  return b ? b->e.set_base_temperature(i, T) : OLB_E_ARG;
+}
 olb_status olb_batch_set_tile_order(olb_batch* b, int32_t strip) {
   return b ? b->e.set_tile_order(strip) : OLB_E_ARG;
 }

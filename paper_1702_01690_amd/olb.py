@@ -64,6 +64,7 @@ _SIGS = {
     "olb_set_f": ([_vp, _dp], ctypes.c_int),
     "olb_wall_density": ([_vp, _dp, _dp], ctypes.c_int),
     "olb_set_tile": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "olb_set_base_temperature": ([_vp, ctypes.c_double], ctypes.c_int),
     "olb_set_tile_order": ([_vp, ctypes.c_int32], ctypes.c_int),
     "olb_batch_set_tile_order": ([_vp, ctypes.c_int32], ctypes.c_int),
     "olb_launch_counts": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -81,6 +82,7 @@ _SIGS = {
     "olb_batch_wall_density": ([_vp, ctypes.c_int32, _dp, _dp], ctypes.c_int),
     "olb_batch_use_graph": ([_vp, ctypes.c_int32], ctypes.c_int),
     "olb_batch_set_tile": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "olb_batch_set_base_temperature": ([_vp, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
     "olb_batch_autotune": ([_vp, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "olb_batch_tiles": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "olb_batch_last_error": ([_vp], ctypes.c_char_p),
@@ -201,6 +203,10 @@ def olb_set_tile(h, by):
     _check(lib().olb_set_tile(h, int(by)), h)
 
 
+def olb_set_base_temperature(h, T):
+    _check(lib().olb_set_base_temperature(h, float(T)), h)
+
+
 def olb_set_tile_order(h, strip):
     _check(lib().olb_set_tile_order(h, int(strip)), h)
 
@@ -291,6 +297,10 @@ class Lattice:
     def set_tile(self, by):
         olb_set_tile(self.h, by)
 
+    def set_base_temperature(self, T):
+        """FP32 departure base at rest and temperature T (default 1)."""
+        olb_set_base_temperature(self.h, T)
+
     def set_tile_order(self, strip):
         olb_set_tile_order(self.h, strip)
 
@@ -372,6 +382,10 @@ def olb_batch_use_graph(h, steps_per_graph):
 
 def olb_batch_set_tile(h, by):
     _check(lib().olb_batch_set_tile(h, int(by)), h, True)
+
+
+def olb_batch_set_base_temperature(h, i, T):
+    _check(lib().olb_batch_set_base_temperature(h, int(i), float(T)), h, True)
 
 
 def olb_batch_set_tile_order(h, strip):
@@ -469,6 +483,10 @@ class Batch:
 
     def set_tile(self, by):
         olb_batch_set_tile(self.h, by)
+
+    def set_base_temperature(self, i, T):
+        """FP32 departure base of instance i at rest and temperature T."""
+        olb_batch_set_base_temperature(self.h, i, T)
 
     def set_tile_order(self, strip):
         olb_batch_set_tile_order(self.h, strip)

@@ -411,16 +411,20 @@ def test_density_steps_degenerate_weno_faces(steps):
     assert err32["n"] < 1e-5, err32
 
 
-@pytest.mark.parametrize("workload,precision,steps,bound", [("wave2048", 0, 20, 1e-13),
-                                                            ("spinodal4096", 1, 10, 1e-7)])
-def test_full_size_periodic_lattice_conserves_mass(workload, precision, steps, bound):
+@pytest.mark.parametrize("workload,precision,tbase,steps,bound", [("wave2048", 0, None, 20, 1e-13),
+                                                                  ("spinodal4096", 1, None, 10, 1e-7),
+                                                                  ("spinodal4096", 1, "T", 10, 1e-10)])
+def test_full_size_periodic_lattice_conserves_mass(workload, precision, tbase, steps, bound):
     """At the benchmark's full sizes and launch configuration, a periodic
     lattice keeps its total mass: every face flux is reconstructed once per
     face and shared by the two nodes beside it (top faces included), the
     collision and the force term leave the density unchanged.  In FP64 the
-    total moves by rounding alone (1e-16); FP32 departure storage drifts
-    steadily by about 1e-9 per step (measured 1.1e-8 over these 10 steps), so
-    its bound is that rate with a tenfold margin."""
+    total moves by rounding alone (1e-16).  FP32 departure storage with the
+    default base (the equilibrium at T = 1) drifts steadily, by about 1e-9 per
+    step at T = 0.514 (measured 1.1e-8 over these 10 steps; its bound is that
+    with a tenfold margin): the departures are large there and their rounding
+    is alike at every node.  With the base at the state's temperature the
+    departures are small and the drift falls below 1e-10."""
     olb = _olb()
     if workload == "wave2048":
         case = I.wave2048()
@@ -428,8 +432,10 @@ def test_full_size_periodic_lattice_conserves_mass(workload, precision, steps, b
         case = I.spinodal(4096, 4096)
         case.params["rho_ref"] = I.N_CRIT
     case.params["precision"] = precision
-    print(f"[parity] mass {workload} precision={precision} steps={steps}", flush=True)
+    print(f"[parity] mass {workload} precision={precision} base={tbase} steps={steps}", flush=True)
     lat = olb.Lattice(case.params)
+    if tbase == "T":
+        lat.set_base_temperature(float(np.mean(case.T)))
     lat.set_fields(*case.fields)
     m0 = float(np.sum(lat.moments()[0], dtype=np.float64))
     lat.step(steps)
@@ -439,3 +445,32 @@ def test_full_size_periodic_lattice_conserves_mass(workload, precision, steps, b
     drift = abs(m1 / m0 - 1.0)
     print(f"[parity] {workload}: total mass {m0:.15e} -> {m1:.15e}, relative drift {drift:.2e}", flush=True)
     assert drift < bound
+
+
+
+def test_fp32_base_temperature_parity_and_rebase():
+    """FP32 storage with its departure base at the state's temperature:
+    density within 1e-5 of the FP64 oracle (spinodal 64^2, 10 steps), and a
+    base changed on a live state leaves the distribution unchanged to FP32
+    rounding; a non-positive base temperature is rejected."""
+    olb = _olb()
+    case = CASES["spinodal64"]()
+    p = dict(case.params, precision=1, rho_ref=float(np.mean(case.n)))
+    lat = olb.Lattice(p)
+    lat.set_base_temperature(float(np.mean(case.T)))
+    lat.set_fields(*case.fields)
+    lat.step(10)
+    lat.sync()
+    gm = lat.moments()
+    om, _, _ = _oracle_cached("spinodal64", 10)
+    err = moment_errors(gm, om)
+    print(f"[parity] spinodal64 FP32, base at T: {err}", flush=True)
+    assert err["n"] < 1e-5, err
+    f0 = lat.get_f()
+    lat.set_base_temperature(1.0)
+    f1 = lat.get_f()
+    scale = np.max(np.abs(f0))
+    assert np.max(np.abs(f1 - f0)) < 1e-6 * scale
+    with pytest.raises(olb.OlbError):
+        lat.set_base_temperature(0.0)
+    lat.close()

@@ -99,6 +99,10 @@ WORKLOADS = {
     "laplace": "Laplace pressure test (Sec. 6): gas bubbles of R0 = 0.15..0.35 in the corner of a 160x160 FP64 "
                "box (specular planes on three sides, diffuse wall at T_w = 0.8), a=9/8 b=1/3, ds=1/320, dt=2e-4, "
                "tau=5e-3, sigma = 5e-5 and 1e-4; 10 instances in one batch, 4e5 steps; planar columns for gamma_pl",
+    "precision4096": "4096x4096 periodic spinodal decomposition at T=0.9 T_c (n=3.5(1+-1% noise), seed 3, "
+                     "tau=0.005, dt=2e-4, ds=1/320), 5000 RK3 steps in FP32-mixed storage (departure base "
+                     "at the state's T) and in FP64, side by side: density error of FP32 against FP64, "
+                     "mass drift, structure-factor peak and liquid fraction over time",
     "closure": "learned closure: coarse 512x512 FP32-mixed (ds 1/80, dt 8e-4) corrected every 10 steps "
                "by the bf16 conv net, against fine 2048x2048 FP64 (ds 1/320, dt 2e-4); spinodal at "
                "T in [0.75, 0.95] T_c, n = 3.5(1 +- 1% noise), tau = 0.005; 200 coarse steps",
@@ -577,6 +581,98 @@ def run_closure(args):
     print(json.dumps(out))
 
 
+def spinodal_stats(n):
+    """Statistics of a phase-separating density field that stay meaningful
+    when two runs decorrelate pointwise: the first moment of the radially
+    binned structure factor S(k) = |FFT(n - <n>)|^2 / N (k in units of
+    2 pi / L), the wavenumber of its largest bin, the liquid fraction (nodes
+    above the critical density) and the density spread."""
+    import olb_inputs as I
+    ny, nx = n.shape
+    d = n - n.mean()
+    S = np.abs(np.fft.rfft2(d)) ** 2 / d.size
+    ky = np.fft.fftfreq(ny, 1.0 / ny)[:, None]
+    kx = np.arange(S.shape[1])[None, :]
+    k = np.sqrt(kx * kx + ky * ky)
+    w = np.full(S.shape[1], 2.0)          # rfft columns stand for +-kx
+    w[0] = 1.0
+    if nx % 2 == 0:
+        w[-1] = 1.0
+    Sw = S * w[None, :]
+    mask = k > 0
+    k1 = float((k * Sw)[mask].sum() / Sw[mask].sum())
+    kb = np.rint(k).astype(np.int64)
+    tot = np.bincount(kb.ravel(), Sw.ravel())
+    cnt = np.bincount(kb.ravel(), np.broadcast_to(w[None, :], S.shape).ravel())
+    prof = tot[1:] / np.maximum(cnt[1:], 1)
+    return {"k1": k1, "k_peak": int(np.argmax(prof) + 1), "liquid_fraction": float((n > I.N_CRIT).mean()),
+            "n_std": float(d.std()), "n_min": float(n.min()), "n_max": float(n.max())}
+
+
+def run_precision(args):
+    """The 4096^2 spinodal of the FP32-mixed workload advanced to its full
+    horizon in FP32-mixed storage and in FP64 from the same input: the
+    density error of FP32 against the FP64 run, both runs' mass drift, and
+    statistics that survive the pointwise decorrelation of a chaotic
+    coarsening (structure factor, liquid fraction), at checkpoints; then the
+    speeds of the two forms on the same lattice."""
+    import torch
+    import olb_inputs as I
+    from paper_1702_01690_amd import olb
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    c = I.spinodal(4096, 4096)
+    p64 = dict(c.params, precision=0)
+    p32 = dict(c.params, precision=1, rho_ref=I.N_CRIT)
+    l64 = olb.Lattice(p64, device="cuda:0")
+    l32 = olb.Lattice(p32, device="cuda:0")
+    l32.set_base_temperature(float(np.mean(c.T)))
+    l64.set_fields(*c.fields)
+    l32.set_fields(*c.fields)
+    m0 = float(c.n.sum())
+    checkpoints = [int(s) for s in args.precision_checkpoints.split(",")]
+    rows, done, secs = [], 0, {"fp64": 0.0, "fp32": 0.0}
+    for target in checkpoints:
+        k = target - done
+        for name, lat in (("fp64", l64), ("fp32", l32)):
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(lat.stream)
+            lat.step(k)
+            ev1.record(lat.stream)
+            lat.sync()
+            secs[name] += ev0.elapsed_time(ev1) / 1e3
+        done = target
+        n64 = l64.moments()[0]
+        n32 = l32.moments()[0]
+        err = np.abs(n32 - n64) / np.abs(n64)
+        row = {"step": done, "t": done * c.params["dt"],
+               "n_max_rel_err": float(err.max()), "n_rms_rel_err": float(np.sqrt(np.mean(err * err))),
+               "mass_drift_fp64": float((n64.sum() - m0) / m0), "mass_drift_fp32": float((n32.sum() - m0) / m0),
+               "fp64": spinodal_stats(n64), "fp32": spinodal_stats(n32)}
+        rows.append(row)
+        log(json.dumps(row))
+    cells = c.params["nx"] * c.params["ny"]
+    ml = {name: cells * done / s / 1e6 for name, s in secs.items()}
+    l64.close()
+    l32.close()
+    out = {
+        "metric": "MLUPS per full RK3 step (D2Q25)",
+        "value": round(ml["fp32"], 2), "unit": "MLUPS", "n_gpus": 1, "steps": done, "warmup": 0,
+        "ms_per_step": round(secs["fp32"] / done * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "precision4096", "description": WORKLOADS["precision4096"], "nodes": cells,
+                   "mlups": {k: round(v, 1) for k, v in ml.items()},
+                   "speedup_fp32_over_fp64": round(ml["fp32"] / ml["fp64"], 3),
+                   "timed": "stepping only, both forms over the whole horizon (read-outs excluded)",
+                   "checkpoints": rows},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 class _Sequential:
     """Single-instance lattices stepped one after another (same stream)."""
 
@@ -623,6 +719,8 @@ def main():
     ap.add_argument("--closure-held-seeds", default="6000,6001,6002,6003",
                     help="held-out 2048^2 samples the closure is evaluated on (the first also "
                          "gives the free runs and the timing)")
+    ap.add_argument("--precision-checkpoints", default="20,100,250,500,1000,2000,3000,4000,5000",
+                    help="steps at which the precision4096 workload compares FP32 with FP64")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -649,6 +747,9 @@ def main():
         return
     if args.workload == "laplace":
         run_laplace(args)
+        return
+    if args.workload == "precision4096":
+        run_precision(args)
         return
 
     import torch

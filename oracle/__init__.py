@@ -71,6 +71,7 @@ def lib():
         L.oolb_step.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.oolb_rhs.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.oolb_wall_density.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.oolb_wall_ghosts.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.oolb_last_error.argtypes = [ctypes.c_void_p]
         L.oolb_last_error.restype = ctypes.c_char_p
         L.oolb_set_threads.argtypes = [ctypes.c_int]
@@ -233,6 +234,14 @@ class Oracle:
         L = np.zeros_like(f)
         self._check(lib().oolb_rhs(self._h, _ptr(f), _ptr(L)))
         return L
+
+    def wall_ghosts(self):
+        """Ghost rows of the last ghost fill, two arrays [25][3][nx]: layer j
+        is row -1 - j (lower wall) and row ny + j (upper wall)."""
+        lo = np.zeros((25, 3, self.nx))
+        hi = np.zeros((25, 3, self.nx))
+        self._check(lib().oolb_wall_ghosts(self._h, _ptr(lo), _ptr(hi)))
+        return lo, hi
 
     def wall_density(self):
         lo = np.zeros(self.nx)

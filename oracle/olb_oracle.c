@@ -601,6 +601,14 @@ static void fill_wall_ghosts(oolb_ctx* c, const double* f) {
   }
 }
 
+int oolb_wall_ghosts(const oolb_ctx* c, double* glo, double* ghi) {
+  if (!c || !glo || !ghi) return OOLB_E_ARG;
+  if (c->p.bc_y == OOLB_BC_PERIODIC) return OOLB_E_STATE;
+  memcpy(glo, c->glo, KV * 3 * (size_t)c->nx * sizeof(double));
+  memcpy(ghi, c->ghi, KV * 3 * (size_t)c->nx * sizeof(double));
+  return OOLB_OK;
+}
+
 int oolb_wall_density(const oolb_ctx* c, double* nw_lo, double* nw_hi) {
   if (!c || !nw_lo || !nw_hi) return OOLB_E_ARG;
   if (c->p.bc_y == OOLB_BC_PERIODIC) return OOLB_E_STATE;

@@ -73,6 +73,10 @@ int oolb_moments(const oolb_ctx* c, double* n, double* ux, double* uy, double* T
 int oolb_rhs(oolb_ctx* c, const double* f, double* L);
 /* Wall densities n_w [nx] of the most recent ghost fill (walls only). */
 int oolb_wall_density(const oolb_ctx* c, double* nw_lo, double* nw_hi);
+/* Ghost rows of the most recent ghost fill (walls only), [25][3][nx] per
+ * wall: layer j of the lower wall is row y = -1 - j, of the upper wall row
+ * y = ny + j. */
+int oolb_wall_ghosts(const oolb_ctx* c, double* glo, double* ghi);
 const char* oolb_last_error(const oolb_ctx* c);
 void oolb_set_threads(int n);
 int oolb_get_threads(void);

@@ -25,7 +25,6 @@
 
 #include "../../include/olb.h"
 #include "olb_consts.hpp"
-#include "olb_consts.hpp"
 #include "olb_device.hpp"
 
 namespace {

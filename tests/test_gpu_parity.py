@@ -34,7 +34,9 @@ def _olb():
     return olb
 
 
-def run_gpu(case, steps, precision=0, by=None, rho_ref=None):
+def run_gpu(case, steps, precision=0, by=None, rho_ref=None, tbase=None):
+    """tbase: FP32 departure base temperature (None: the default T = 1;
+    "T": the mean initial temperature, as the benchmark sets it)."""
     olb = _olb()
     p = dict(case.params)
     p["precision"] = precision
@@ -43,6 +45,8 @@ def run_gpu(case, steps, precision=0, by=None, rho_ref=None):
     lat = olb.Lattice(p)
     if by:
         lat.set_tile(by)
+    if tbase is not None:
+        lat.set_base_temperature(float(np.mean(case.T)) if tbase == "T" else float(tbase))
     lat.set_fields(*case.fields)
     lat.step(steps)
     lat.sync()
@@ -118,10 +122,10 @@ def _tolerance(name, steps):
     return tol
 
 
-def _compare(name, steps, precision=0, tol=TOL64):
+def _compare(name, steps, precision=0, tol=TOL64, tbase=None):
     case = CASES[name]()
-    print(f"[parity] {name} steps={steps} precision={precision}", flush=True)
-    gm, gf, gnw = run_gpu(case, steps, precision=precision)
+    print(f"[parity] {name} steps={steps} precision={precision} base={tbase}", flush=True)
+    gm, gf, gnw = run_gpu(case, steps, precision=precision, tbase=tbase)
     om, of, onw = _oracle_cached(name, steps)
     err = moment_errors(gm, om)
     ferr = float(np.max(np.abs(gf - of)) / np.max(np.abs(of)))
@@ -204,6 +208,24 @@ def test_box_equals_mirror_symmetric_periodic_domain():
     assert rel_scalar(b.wall_density()[1], a.wall_density()[1][:70]) < TOL64
 
 
+@pytest.mark.parametrize("name,steps", [("channel64x128", 10), ("channel67x20", 30), ("half40x70", 10),
+                                        ("half67x9", 20), ("box70x37", 10), ("box130x9", 20)])
+def test_fp32_base_at_state_temperature_matches_oracle(name, steps):
+    """FP32 storage with its departure base at the state's mean temperature
+    (the benchmark's setting) on walled lattices: the ghost rows of the walls
+    (Eq. nw, the wall Maxwellian minus the base) and the mirror planes then
+    run through the base-dependent code.  Density within 1e-5 of the FP64
+    oracle, and the wall densities too."""
+    err, _, gnw, onw = _compare(name, steps, precision=1, tbase="T")
+    assert err["n"] < 1e-5, err
+    if gnw is not None:
+        for g, o in zip(gnw, onw):
+            if np.any(o != 0.0):
+                assert rel_scalar(g, o) < 1e-5
+            else:
+                assert np.all(g == 0.0)
+
+
 def test_fp32_specular_half_channel_density_within_1e5():
     err, _, _, _ = _compare("half40x70", 10, precision=1)
     assert err["n"] < 1e-5, err
@@ -264,20 +286,26 @@ def test_fp64_wave2048_full_size_equals_tiled_crop():
     assert max(err.values()) < TOL64, err
 
 
-def test_fp32_spinodal4096_full_size_equals_tiled_crop():
+@pytest.mark.parametrize("tbase", ["T", None])
+def test_fp32_spinodal4096_full_size_equals_tiled_crop(tbase):
     """The 4096^2 FP32 benchmark configuration (departure storage about
-    rho_ref = n_c, default tiles and order): started from a 64^2 noisy
-    spinodal field tiled 64 x 64, it stays equal to the 64^2 run tiled --
-    bitwise, every node does the same arithmetic -- while the 64^2 FP32 run
-    is checked against the oracle elsewhere."""
+    rho_ref = n_c with the base at the state's temperature, as the benchmark
+    runs it, and with the default base; default tiles and order): started
+    from a 64^2 noisy spinodal field tiled 64 x 64, it stays equal to the
+    64^2 run tiled -- bitwise, every node does the same arithmetic -- and the
+    64^2 FP32 run is within 1e-5 in density of the oracle."""
     crop = I.spinodal(64, 64, steps=20)
     full = I.spinodal(64, 64, steps=20)
     full.params.update(nx=4096, ny=4096)
     fields = tuple(np.tile(a, (64, 64)) for a in crop.fields)
     full = I.Case("spinodal4096tiled", full.params, *fields, 20)
-    print("[parity] spinodal 4096^2 FP32 from a tiled 64^2 field, 20 steps", flush=True)
-    gm, _, _ = run_gpu(full, 20, precision=1, rho_ref=I.N_CRIT)
-    cm, _, _ = run_gpu(crop, 20, precision=1, rho_ref=I.N_CRIT)
+    # one base value for both runs (a mean over 4096^2 equal temperatures can
+    # round differently from the mean over 64^2 of them)
+    if tbase == "T":
+        tbase = float(np.mean(crop.T))
+    print(f"[parity] spinodal 4096^2 FP32 from a tiled 64^2 field, 20 steps, base {tbase}", flush=True)
+    gm, _, _ = run_gpu(full, 20, precision=1, rho_ref=I.N_CRIT, tbase=tbase)
+    cm, _, _ = run_gpu(crop, 20, precision=1, rho_ref=I.N_CRIT, tbase=tbase)
     for a, b in zip(gm, cm):
         np.testing.assert_array_equal(a, np.tile(b, (64, 64)))
     om, _, _ = _oracle_cached("spinodal64", 20)

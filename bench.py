@@ -129,28 +129,62 @@ def make_cases(workload):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def cpu_baseline(workload, sample_steps):
-    """The oracle, as it stands, on the 64 x 64 crop of the wave workload (the
-    2048^2 field is this crop tiled, so the per-cell work is identical)."""
+def cpu_baseline(workload, min_seconds):
+    """The oracle, as it stands, on a bounded sample of the workload itself:
+    whole instances at their full size (the 2048^2 lattice of the default
+    workload; the first channels of the batch), one RK-3 step at a time
+    until min_seconds of stepping have passed (at least one step), on all of
+    the host's threads; then one thread on a 256^2 lattice of the same
+    physics for about min_seconds."""
     import olb_inputs as I
     import oracle
+    threads = oracle.get_threads()
+    cells_steps, secs, used = 0, 0.0, []
+    for case in make_cases(workload):
+        o = oracle.Oracle(case.params)
+        o.set_fields(*case.fields)
+        cells = case.params["nx"] * case.params["ny"]
+        steps = 0
+        while secs < min_seconds:
+            t0 = time.perf_counter()
+            o.step(1)
+            secs += time.perf_counter() - t0
+            steps += 1
+            cells_steps += cells
+            if case.params.get("bc_y", 0) != 0:
+                break                      # channels: one step each, then the next channel
+        o.close()
+        used.append(f"{case.params['nx']}x{case.params['ny']} x {steps}")
+        if secs >= min_seconds:
+            break
+    full = {"value": cells_steps / secs / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle on full-size instances of the workload ({', '.join(used)} RK3 steps), "
+                      f"{secs:.1f} s of stepping on {threads} threads"}
+    # one thread on a lattice that does not fit in the caches either
     if workload == "wave2048":
-        case = I.wave64()
+        small = I.tile(I.wave64(), 4, 4)
     elif workload == "spinodal4096":
-        case = I.spinodal(64, 64)
+        small = I.spinodal(256, 256)
     else:
-        case = I.channel(64, 128, tw=0.8 * I.T_CRIT)
-    o = oracle.Oracle(case.params)
-    o.set_fields(*case.fields)
-    o.step(1)
-    t0 = time.perf_counter()
-    o.step(sample_steps)
-    dt = time.perf_counter() - t0
-    cells = case.params["nx"] * case.params["ny"]
-    return {"value": cells * sample_steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.get_threads(),
-            "kind": "oracle",
-            "sample": f"{case.params['nx']}x{case.params['ny']} lattice of the same physics (FP64 oracle), "
-                      f"{sample_steps} RK3 steps, {dt:.1f} s"}
+        small = I.channel(256, 256, tw=0.8 * I.T_CRIT)
+    oracle.set_threads(1)
+    try:
+        o = oracle.Oracle(small.params)
+        o.set_fields(*small.fields)
+        steps, t1 = 0, 0.0
+        while t1 < min_seconds:
+            t0 = time.perf_counter()
+            o.step(1)
+            t1 += time.perf_counter() - t0
+            steps += 1
+        o.close()
+    finally:
+        oracle.set_threads(threads)
+    cells = small.params["nx"] * small.params["ny"]
+    full["one_core"] = {"value": cells * steps / t1 / 1e6, "unit": "MLUPS", "cores": 1,
+                        "sample": f"{small.params['nx']}x{small.params['ny']} lattice of the same physics, "
+                                  f"{steps} RK3 steps, {t1:.1f} s on 1 thread"}
+    return full
 
 
 def copy_kernel(gib, reps=10):
@@ -615,7 +649,9 @@ def run_precision(args):
     density error of FP32 against the FP64 run, both runs' mass drift, and
     statistics that survive the pointwise decorrelation of a chaotic
     coarsening (structure factor, liquid fraction), at checkpoints; then the
-    speeds of the two forms on the same lattice."""
+    speeds of the two forms on the same lattice.  A third run, FP64 from the
+    inputs rounded to FP32, gives the error that rounding the state once
+    produces by itself (the condition of the problem)."""
     import torch
     import olb_inputs as I
     from paper_1702_01690_amd import olb
@@ -628,27 +664,40 @@ def run_precision(args):
     p32 = dict(c.params, precision=1, rho_ref=I.N_CRIT)
     l64 = olb.Lattice(p64, device="cuda:0")
     l32 = olb.Lattice(p32, device="cuda:0")
+    # the condition of the problem: FP64 from the inputs rounded to FP32
+    lrd = olb.Lattice(p64, device="cuda:0")
     l32.set_base_temperature(float(np.mean(c.T)))
     l64.set_fields(*c.fields)
     l32.set_fields(*c.fields)
+    r32 = lambda a: a.astype(np.float32).astype(np.float64)
+    lrd.set_fields(*(r32(a) for a in c.fields))
     m0 = float(c.n.sum())
     checkpoints = [int(s) for s in args.precision_checkpoints.split(",")]
     rows, done, secs = [], 0, {"fp64": 0.0, "fp32": 0.0}
+
+    def errors(a, ref):
+        e = np.abs(a - ref) / np.abs(ref)
+        return float(e.max()), float(np.sqrt(np.mean(e * e))), float(np.quantile(e, 0.999))
+
     for target in checkpoints:
         k = target - done
-        for name, lat in (("fp64", l64), ("fp32", l32)):
+        for name, lat in (("fp64", l64), ("fp32", l32), ("rounded", lrd)):
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ev0.record(lat.stream)
             lat.step(k)
             ev1.record(lat.stream)
             lat.sync()
-            secs[name] += ev0.elapsed_time(ev1) / 1e3
+            if name in secs:
+                secs[name] += ev0.elapsed_time(ev1) / 1e3
         done = target
         n64 = l64.moments()[0]
         n32 = l32.moments()[0]
-        err = np.abs(n32 - n64) / np.abs(n64)
+        nrd = lrd.moments()[0]
+        emax, erms, e999 = errors(n32, n64)
+        smax, srms, s999 = errors(nrd, n64)
         row = {"step": done, "t": done * c.params["dt"],
-               "n_max_rel_err": float(err.max()), "n_rms_rel_err": float(np.sqrt(np.mean(err * err))),
+               "n_max_rel_err": emax, "n_rms_rel_err": erms, "n_q999_rel_err": e999,
+               "fp64_from_fp32_inputs": {"n_max_rel_err": smax, "n_rms_rel_err": srms, "n_q999_rel_err": s999},
                "mass_drift_fp64": float((n64.sum() - m0) / m0), "mass_drift_fp32": float((n32.sum() - m0) / m0),
                "fp64": spinodal_stats(n64), "fp32": spinodal_stats(n32)}
         rows.append(row)
@@ -657,6 +706,7 @@ def run_precision(args):
     ml = {name: cells * done / s / 1e6 for name, s in secs.items()}
     l64.close()
     l32.close()
+    lrd.close()
     out = {
         "metric": "MLUPS per full RK3 step (D2Q25)",
         "value": round(ml["fp32"], 2), "unit": "MLUPS", "n_gpus": 1, "steps": done, "warmup": 0,
@@ -702,8 +752,8 @@ def main():
     ap.add_argument("--graph", type=int, default=10, help="RK3 steps per HIP graph (batches)")
     ap.add_argument("--autotune", action="store_true", help="pick the tile height by trial (batches)")
     ap.add_argument("--tile", type=int, default=8, choices=[8, 16])
-    ap.add_argument("--cpu-steps", type=int, default=2000,
-                    help="oracle steps of the CPU-baseline sample (about 10-20 s on 16 threads)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="stepping time of each CPU-baseline leg (the oracle on all threads, then one)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "fp32"],
                     help="override the workload's storage precision (speedup comparisons)")
@@ -860,7 +910,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.workload, args.cpu_steps)
+        cpu = cpu_baseline(args.workload, args.cpu_seconds)
 
     out = {
         "metric": "MLUPS per full RK3 step (D2Q25)",

@@ -13,7 +13,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: longer CPU runs of the oracle")
+    config.addinivalue_line("markers", "slow: long runs (oracle studies on the CPU, validation studies on the GPU)")
 
 
 def golden(name):

@@ -290,6 +290,24 @@ olb_status olb_closure_nudge(olb_closure* c, olb_ctx* coarse, const double* dev_
 const char* olb_closure_last_error(const olb_closure* c);
 void olb_closure_free(olb_closure* c);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid hipMalloc): olb_closure_forward without
+ * a closure object or workspace.  Same kernels and result (network output of
+ * dev_moments, device double [4][ny][nx], scaled by out_scale and projected
+ * by conserve_mask, into dev_delta, device double [4][ny][nx]); the
+ * parameters come from dev_params, device FP32 [OLB_CLOSURE_NPARAM] in the
+ * layout above, and the normalisation from the host arrays (as
+ * olb_closure_set_norm).  The bf16 weight matrices and the projection's
+ * channel sums live in a static device array of 32 KiB that the library
+ * holds on every GPU it runs on until the process ends; the call allocates
+ * nothing and enqueues three kernels on hip_stream (no memset).  Every call
+ * on a GPU overwrites that array: calls that overlap on one GPU (other
+ * streams, other threads) race.  nx, ny >= 1 with nx * ny < 2^30 and mask in
+ * 0..15, else OLB_E_ARG; non-positive scales: OLB_E_ARG.  Asynchronous. */
+olb_status olb_closure_forward_noalloc(int32_t nx, int32_t ny, const float* dev_params, const double in_mean[4],
+                                       const double in_scale[4], const double out_scale[4], int32_t conserve_mask,
+                                       const double* dev_moments, double* dev_delta, void* hip_stream);
+
 /* Conservative restriction of fine moment planes [4][fny][fnx] to coarse
  * planes [4][fny/factor][fnx/factor]: n, n u and n (u^2 + 2T) (m = 1, D = 2)
  * are averaged over factor x factor blocks, then u and T recovered.  Both

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -348,11 +349,14 @@ __global__ void loss_kernel(const float* __restrict__ Z3, const double* __restri
   if (threadIdx.x == 0) atomicAdd(loss, part[0] / (4.0f * (float)P));
 }
 
-// FP32 master parameters -> bf16 weight matrices (padded) of the three layers
+// FP32 master parameters -> bf16 weight matrices (padded) of the three layers;
+// clear4, when not null, gets four zeros (the projection's channel sums, so
+// that no memset has to be enqueued)
 __global__ void pack_weights(const float* __restrict__ w, bf16* __restrict__ W1, bf16* __restrict__ W2,
-                             bf16* __restrict__ W3) {
+                             bf16* __restrict__ W3, double* __restrict__ clear4) {
   // layer l: Cin, Cout, offset of W in the flat vector
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (clear4 && idx < 4) clear4[idx] = 0.0;
   constexpr int KP1 = kp_of(4), KP2 = kp_of(32), KP3 = kp_of(32);
   constexpr int N1 = 32 * KP1, N2 = 32 * KP2, N3 = 16 * KP3;
   constexpr int O1 = 0, O2 = 32 * 4 * 9 + 32, O3 = O2 + 32 * 32 * 9 + 32;
@@ -617,6 +621,26 @@ __global__ void apply_kernel(const double* __restrict__ m, const double* __restr
 }  // namespace olbk
 
 // --------------------------------------------------------------------------
+// device scratch of the allocation-free inference entry point
+// --------------------------------------------------------------------------
+// The bf16 weight matrices of the three layers and the projection's four
+// channel sums.  One copy per GPU, held until the process ends; every call
+// on a GPU overwrites it.  In host code the name stands for a host-side
+// stand-in: kernels and copies get its device address from
+// hipGetSymbolAddress (noalloc_scratch below), never the name itself.
+namespace {
+constexpr size_t NA_W1 = 0;
+constexpr size_t NA_W2 = NA_W1 + 32 * olbk::kp_of(4) * sizeof(olbk::bf16);
+constexpr size_t NA_W3 = NA_W2 + 32 * olbk::kp_of(32) * sizeof(olbk::bf16);
+constexpr size_t NA_SUMS = NA_W3 + 16 * olbk::kp_of(32) * sizeof(olbk::bf16);
+constexpr size_t NA_USED = NA_SUMS + 4 * sizeof(double);
+constexpr size_t NA_BYTES = 32768;
+static_assert(NA_USED <= NA_BYTES, "scratch layout");
+static_assert(NA_SUMS % 8 == 0, "sums alignment");
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+// --------------------------------------------------------------------------
 // host side
 // --------------------------------------------------------------------------
 
@@ -797,7 +821,7 @@ struct olb_closure {
     using namespace olbk;
     const int n = 32 * kp_of(4) + 32 * kp_of(32) + 16 * kp_of(32);
     hipLaunchKernelGGL(pack_weights, dim3((n + 255) / 256), dim3(256), 0, stream, at<float>(L.par),
-                       at<bf16>(L.w1), at<bf16>(L.w2), at<bf16>(L.w3));
+                       at<bf16>(L.w1), at<bf16>(L.w2), at<bf16>(L.w3), nullptr);
     return hip(hipGetLastError(), "weight pack");
   }
 };
@@ -1008,6 +1032,66 @@ olb_status olb_restrict(const double* dev_fine, int32_t fnx, int32_t fny, int32_
   const int cnx = fnx / factor, cny = fny / factor;
   hipLaunchKernelGGL(olbk::restrict_kernel, dim3((cnx + 63) / 64, cny), dim3(64), 0, (hipStream_t)hip_stream,
                      dev_fine, fnx, fny, factor, dev_coarse);
+  return hipGetLastError() == hipSuccess ? OLB_OK : OLB_E_DEVICE;
+}
+
+}  // extern "C"
+
+namespace {
+// Device address of `scratch` on the current device, looked up once per
+// device (each GPU holds its own copy at its own address).
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mutex;
+void* na_ptr[NA_MAX_DEVICES] = {};
+
+olb_status noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NA_MAX_DEVICES) return OLB_E_DEVICE;
+  std::lock_guard<std::mutex> lock(na_mutex);
+  if (!na_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return OLB_E_DEVICE;
+    na_ptr[dev] = p;
+  }
+  *out = na_ptr[dev];
+  return OLB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+olb_status olb_closure_forward_noalloc(int32_t nx, int32_t ny, const float* dev_params, const double in_mean[4],
+                                       const double in_scale[4], const double out_scale[4], int32_t conserve_mask,
+                                       const double* dev_moments, double* dev_delta, void* hip_stream) {
+  using namespace olbk;
+  if (!dev_params || !in_mean || !in_scale || !out_scale || !dev_moments || !dev_delta) return OLB_E_ARG;
+  if (!valid_size(nx, ny) || conserve_mask < 0 || conserve_mask > 15) return OLB_E_ARG;
+  Norm nm;
+  for (int k = 0; k < 4; ++k) {
+    if (!(in_scale[k] > 0.0) || !(out_scale[k] > 0.0) || !std::isfinite(in_mean[k])) return OLB_E_ARG;
+    nm.in_mean[k] = (float)in_mean[k];
+    nm.in_inv_scale[k] = (float)(1.0 / in_scale[k]);
+    nm.out_scale[k] = (float)out_scale[k];
+  }
+  void* base = nullptr;
+  olb_status s = noalloc_scratch(&base);
+  if (s) return s;
+  unsigned char* sc = static_cast<unsigned char*>(base);
+  bf16* W1 = reinterpret_cast<bf16*>(sc + NA_W1);
+  bf16* W2 = reinterpret_cast<bf16*>(sc + NA_W2);
+  bf16* W3 = reinterpret_cast<bf16*>(sc + NA_W3);
+  double* sums = conserve_mask ? reinterpret_cast<double*>(sc + NA_SUMS) : nullptr;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int n = 32 * kp_of(4) + 32 * kp_of(32) + 16 * kp_of(32);
+  hipLaunchKernelGGL(pack_weights, dim3((n + 255) / 256), dim3(256), 0, st, dev_params, W1, W2, W3, sums);
+  const int tiles_x = (nx + FT - 1) / FT, tiles_y = (ny + FT - 1) / FT;
+  const int P = nx * ny;
+  hipLaunchKernelGGL(infer_kernel, dim3(tiles_x * tiles_y), dim3(512), 0, st, dev_moments, nm, W1, W2, W3,
+                     dev_params + 32 * 4 * 9, dev_params + (32 * 4 * 9 + 32) + 32 * 32 * 9, dev_params + (NPARAM - 4),
+                     nx, ny, tiles_x, dev_delta, sums);
+  if (sums)
+    hipLaunchKernelGGL(project_kernel, dim3((P + 255) / 256), dim3(256), 0, st, dev_delta, P, nm, sums,
+                       conserve_mask);
   return hipGetLastError() == hipSuccess ? OLB_OK : OLB_E_DEVICE;
 }
 

@@ -102,6 +102,8 @@ _SIGS = {
     "olb_closure_apply": ([_vp, _vp, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "olb_closure_set_conserve": ([_vp, ctypes.c_int32], ctypes.c_int),
     "olb_closure_nudge": ([_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "olb_closure_forward_noalloc": ([ctypes.c_int32, ctypes.c_int32, _vp, _dp, _dp, _dp, ctypes.c_int32, _vp, _vp,
+                                     _vp], ctypes.c_int),
     "olb_closure_last_error": ([_vp], ctypes.c_char_p),
     "olb_closure_free": ([_vp], None),
     "olb_restrict": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp], ctypes.c_int),
@@ -580,6 +582,16 @@ def olb_closure_nudge(h, ctx, dev_target, dev_moments=None):
     _check(lib().olb_closure_nudge(h, ctx, _vp(dev_target), _vp(dev_moments) if dev_moments else None,
                                    ctypes.byref(skipped)), h, "closure")
     return skipped.value
+
+
+def olb_closure_forward_noalloc(nx, ny, dev_params, in_mean, in_scale, out_scale, mask, dev_moments, dev_delta,
+                                stream_ptr):
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (in_mean, in_scale, out_scale)]
+    for a in arrs:
+        if a.size != 4:
+            raise ValueError("normalisation vectors have 4 entries")
+    _check(lib().olb_closure_forward_noalloc(int(nx), int(ny), _vp(dev_params), *(_ptr(a) for a in arrs), int(mask),
+                                             _vp(dev_moments), _vp(dev_delta), _vp(stream_ptr)))
 
 
 def olb_closure_set_conserve(h, mask):

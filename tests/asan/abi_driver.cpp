@@ -105,6 +105,11 @@ int main() {
   olb_closure* cl = nullptr;
   expect("closure small workspace", olb_closure_init(64, 48, small, sizeof small, nullptr, &cl), OLB_E_WORKSPACE);
   expect("closure forward", olb_closure_forward(nullptr, d, d), OLB_E_ARG);
+  double one[4] = {1, 1, 1, 1};
+  expect("noalloc null", olb_closure_forward_noalloc(8, 8, nullptr, one, one, one, 0, d, d, nullptr), OLB_E_ARG);
+  float fp[1] = {0};
+  expect("noalloc size", olb_closure_forward_noalloc(0, 8, fp, one, one, one, 0, d, d, nullptr), OLB_E_ARG);
+  expect("noalloc mask", olb_closure_forward_noalloc(8, 8, fp, one, one, one, 16, d, d, nullptr), OLB_E_ARG);
   expect("restrict", olb_restrict(d, 10, 8, 4, d, nullptr), OLB_E_ARG);
   if (failures) {
     std::fprintf(stderr, "%d failures\n", failures);

@@ -96,3 +96,14 @@ def test_closure_validation_without_device_work():
             olb.olb_restrict(1 << 20, fnx, fny, r, 1 << 21, 0)
         assert e.value.code == olb.OLB_E_ARG
     assert L.olb_closure_last_error(None) == b"null closure"
+
+
+def test_noalloc_closure_forward_rejects_null_pointers_on_the_host():
+    """The allocation-free inference call validates its arguments before it
+    touches a device."""
+    import numpy as np
+    olb, L = _lib()
+    one = np.ones(4)
+    with pytest.raises(olb.OlbError) as e:
+        olb.olb_closure_forward_noalloc(8, 8, None, one, one, one, 0, None, None, None)
+    assert e.value.code == olb.OLB_E_ARG

@@ -519,8 +519,9 @@ def run_closure(args):
         samples.append((s.params, s.fields))
     small = olb.Closure(nf_train // factor, nf_train // factor)
     t0 = time.perf_counter()
-    info = C.train_closure(samples, I.coarse_params, small, windows=8, window=window, epochs=args.closure_epochs,
-                           rounds=1, round_epochs=max(1, args.closure_epochs // 2),
+    info = C.train_closure(samples, I.coarse_params, small, windows=args.closure_windows, window=window,
+                           epochs=args.closure_epochs, rounds=args.closure_rounds,
+                           round_epochs=max(1, args.closure_epochs // 2),
                            init_params=I.closure_params(seed=7), seed=1, log=log)
     t_train = time.perf_counter() - t0
     del samples
@@ -604,6 +605,11 @@ def run_closure(args):
                        "free_run_first_window_max": [roll_p[0][0], roll_f[0][0]],
                        "free_run_end_max": [roll_p[-1][0], roll_f[-1][0]],
                        "free_run_end_rms": [roll_p[-1][1], roll_f[-1][1]],
+                       "free_run_by_window": {"coarse_steps": [window * (j + 1) for j in range(len(roll_p))],
+                                              "plain_max": [a for a, _ in roll_p],
+                                              "closure_max": [a for a, _ in roll_f],
+                                              "plain_rms": [b for _, b in roll_p],
+                                              "closure_rms": [b for _, b in roll_f]},
                        "order": "[plain coarse, coarse + closure]", "skipped_nodes": skipped}},
         "roofline": {"bound": "mfma", "kernel": "network forward (fused: one 16x16 tile per workgroup, "
                                "three bf16 implicit-GEMM convolutions in LDS, plus the projection)",
@@ -766,6 +772,10 @@ def main():
     ap.add_argument("--closure-samples", type=int, default=64,
                     help="training trajectories of the closure workload (8 pairs each)")
     ap.add_argument("--closure-epochs", type=int, default=30)
+    ap.add_argument("--closure-windows", type=int, default=8,
+                    help="windows of 10 coarse steps per training trajectory")
+    ap.add_argument("--closure-rounds", type=int, default=1,
+                    help="data-aggregation rounds after the nudged pairs")
     ap.add_argument("--closure-held-seeds", default="6000,6001,6002,6003",
                     help="held-out 2048^2 samples the closure is evaluated on (the first also "
                          "gives the free runs and the timing)")

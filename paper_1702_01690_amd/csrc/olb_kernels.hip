@@ -38,6 +38,32 @@ __device__ __forceinline__ gmem<T>* as_global(T* p) {
   return (gmem<T>*)p;
 }
 
+// Buffer resource over one population plane (plane k of an array of planes
+// of plane_bytes each) and loads / stores through it.  A lane's byte offset
+// within a plane is the same for every population, and the plane base sits in
+// scalar registers, so plane accesses cost the vector ALUs no address
+// arithmetic.  Offsets at or past plane_bytes read 0 and write nothing.
+// (Word 3 of the descriptor: raw 32-bit data, the gfx9 buffer format.)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int k, uint32_t plane_bytes) {
+  const char* p = static_cast<const char*>(base) + (int64_t)k * plane_bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), (short)0, (int)plane_bytes, 0x00020000);
+}
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+template <typename Real>
+__device__ __forceinline__ Real bload(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  if constexpr (sizeof(Real) == 4)
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+  else
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+template <typename Real>
+__device__ __forceinline__ void bstore(Real v, __amdgpu_buffer_rsrc_t r, int byte_off) {
+  if constexpr (sizeof(Real) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, byte_off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, byte_off, 0, 0);
+}
+
 // Value held by lane + 1 of the wavefront (lane 63 receives 0): a DPP
 // wavefront shift by one lane, a VALU move rather than an LDS round trip.
 __device__ __forceinline__ float lane_next(float v) {
@@ -70,13 +96,16 @@ __device__ __forceinline__ float frcp(float d) { return __builtin_amdgcn_rcpf(d)
 // ideal weights restricted to the vanishing candidates.  Indicators are formed
 // from first differences d, so a vanishing indicator is exactly "three equal
 // values".  The weights are scale free, so each indicator is used times 4:
-// s_q = (13/3) a_q^2 + b_q^2.  The unnormalised weights use one reciprocal,
-//   w_q ~ delta_q prod_{r != q} s_r^2,  with delta scaled to (1, 6, 3),
+// s_q = (13/3) a_q^2 + b_q^2.  The normalised weights need one reciprocal:
+//   w_q ~ delta_q prod_{r != q} s_r^2,  delta_q ~ (1, 6, 3),
 // which already gives Tab. weno when one indicator vanishes (that candidate
 // alone keeps a non-zero weight).  When two or more vanish, every candidate
 // that keeps a weight equals f_i (its values are all f_i), so the result is
 // f_i.  The candidates enter through their offsets from f_i, times 6:
-//   e1 = 5 d2 - 2 d1,  e2 = d2 + 2 d3,  e3 = 4 d3 - d4.
+//   e1 = 5 d2 - 2 d1,  e2 = d2 + 2 d3,  e3 = 4 d3 - d4,
+// and the ideal weights and the 1/6 are folded into them: with
+// W1 = (s2 s3)^2, W2 = (s1 s3)^2, W3 = (s1 s2)^2 the face value is
+//   f_i + [W1 e1/6 + W2 e2 + W3 e3/2] / [W1 + 6 W2 + 3 W3].
 __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, double v3, double v4) {
   const double d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
   const double a1 = d2 - d1, b1 = __builtin_fma(3.0, d2, -d1);
@@ -86,47 +115,52 @@ __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, doub
   const double s2 = __builtin_fma(a2 * (13.0 / 3.0), a2, b2 * b2);
   const double s3 = __builtin_fma(a3 * (13.0 / 3.0), a3, b3 * b3);
   const double q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
-  const double w1 = q2 * q3, w2 = 6.0 * (q1 * q3), w3 = 3.0 * (q1 * q2);
-  const double e1 = __builtin_fma(5.0, d2, -2.0 * d1);
-  const double e2 = __builtin_fma(2.0, d3, d2);
-  const double e3 = __builtin_fma(4.0, d3, -d4);
-  const double num = __builtin_fma(w1, e1, __builtin_fma(w2, e2, w3 * e3));
-  const double den = w1 + w2 + w3;
-  const double r = __builtin_fma(num, frcp(6.0 * den), v2);
-  return den == 0.0 ? v2 : r;
+  // 2^-1000 in the second weight keeps den > 0 without a branch (the FP32
+  // form below explains why the result is then f_i when two indicators
+  // vanish); a weight it could disturb would need differences of 1e-36,
+  // far below the rounding of any population value
+  const double w1 = q2 * q3, w2 = __builtin_fma(q1, q3, 0x1p-1000), w3 = q1 * q2;
+  const double g1 = __builtin_fma(5.0 / 6.0, d2, d1 * (-1.0 / 3.0));
+  const double g2 = __builtin_fma(2.0, d3, d2);
+  const double g3 = __builtin_fma(2.0, d3, d4 * -0.5);
+  const double num = __builtin_fma(w1, g1, __builtin_fma(w2, g2, w3 * g3));
+  const double den = __builtin_fma(3.0, w3, __builtin_fma(6.0, w2, w1));
+  return __builtin_fma(num, frcp(den), v2);
 }
 
 // FP32: the weights are products of squared indicators (eighth powers of the
-// differences), which would leave the FP32 range, so each indicator is
-// scaled by 2^-2e, with 2^e bounding the largest difference magnitude m
-// (m = f 2^e, 1/2 <= f < 1).  The scaling is exact and cancels in the
-// weights; the candidate offsets stay unscaled.  An indicator that still
-// underflows acts as a vanishing one, which changes the result by far less
-// than FP32 rounding.
+// differences), which would leave the FP32 range, so the indicators are
+// scaled by 2^-e, with 2^e bounding the largest of them (m = f 2^e,
+// 1/2 <= f < 1): the scaled indicators lie in [0, 1) and the largest in
+// [1/2, 1).  The scaling is exact and cancels in the weights; the candidate
+// offsets stay unscaled.  An indicator that underflows acts as a vanishing
+// one, which changes the result by far less than FP32 rounding (its three
+// values then agree to far below the rounding of f_i).
 __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3, float v4) {
   const float d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
-  const float m = fmaxf(fmaxf(fabsf(d1), fabsf(d2)), fmaxf(fabsf(d3), fabsf(d4)));
-  // -2 e in one 24-bit multiply (|e| <= 150)
-  const int e2 = __mul24(__builtin_amdgcn_frexp_expf(m), -2);
   const float a1 = d2 - d1, b1 = __builtin_fmaf(3.0f, d2, -d1);
   const float a2 = d3 - d2, b2 = d2 + d3;
   const float a3 = d4 - d3, b3 = __builtin_fmaf(3.0f, d3, -d4);
-  const float s1 = __builtin_amdgcn_ldexpf(__builtin_fmaf(a1 * (13.0f / 3.0f), a1, b1 * b1), e2);
-  const float s2 = __builtin_amdgcn_ldexpf(__builtin_fmaf(a2 * (13.0f / 3.0f), a2, b2 * b2), e2);
-  const float s3 = __builtin_amdgcn_ldexpf(__builtin_fmaf(a3 * (13.0f / 3.0f), a3, b3 * b3), e2);
+  const float t1 = __builtin_fmaf(a1 * (13.0f / 3.0f), a1, b1 * b1);
+  const float t2 = __builtin_fmaf(a2 * (13.0f / 3.0f), a2, b2 * b2);
+  const float t3 = __builtin_fmaf(a3 * (13.0f / 3.0f), a3, b3 * b3);
+  const int ne = -__builtin_amdgcn_frexp_expf(fmaxf(fmaxf(t1, t2), t3));
+  const float s1 = __builtin_amdgcn_ldexpf(t1, ne);
+  const float s2 = __builtin_amdgcn_ldexpf(t2, ne);
+  const float s3 = __builtin_amdgcn_ldexpf(t3, ne);
   const float q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
   // 2^-126 in the second weight keeps den > 0 without a branch: den would
   // vanish only with two indicators zero, and then d2 = d3 = 0 (s1 = s2 = 0,
-  // s1 = s3 = 0) or d2 = d3 = d4 = 0 (s2 = s3 = 0), so e2 = 0 and the other
+  // s1 = s3 = 0) or d2 = d3 = d4 = 0 (s2 = s3 = 0), so g2 = 0 and the other
   // two weights vanish: num = 0 and the result is f_i, as the rule above
   // requires.  Elsewhere it moves den by 1e-37 at most.
-  const float w1 = q2 * q3, w2 = 6.0f * __builtin_fmaf(q1, q3, 0x1p-126f), w3 = 3.0f * (q1 * q2);
-  const float e1 = __builtin_fmaf(5.0f, d2, -2.0f * d1);
-  const float ee2 = __builtin_fmaf(2.0f, d3, d2);
-  const float e3 = __builtin_fmaf(4.0f, d3, -d4);
-  const float num = __builtin_fmaf(w1, e1, __builtin_fmaf(w2, ee2, w3 * e3));
-  const float den = w1 + w2 + w3;
-  return __builtin_fmaf(num, frcp(6.0f * den), v2);
+  const float w1 = q2 * q3, w2 = __builtin_fmaf(q1, q3, 0x1p-126f), w3 = q1 * q2;
+  const float g1 = __builtin_fmaf(5.0f / 6.0f, d2, d1 * (-1.0f / 3.0f));
+  const float g2 = __builtin_fmaf(2.0f, d3, d2);
+  const float g3 = __builtin_fmaf(2.0f, d3, d4 * -0.5f);
+  const float num = __builtin_fmaf(w1, g1, __builtin_fmaf(w2, g2, w3 * g3));
+  const float den = __builtin_fmaf(3.0f, w3, __builtin_fmaf(6.0f, w2, w1));
+  return __builtin_fmaf(num, frcp(den), v2);
 }
 
 // FP32 departure base: f = rho0 b_kx b_ky + stored value, with per-axis
@@ -346,9 +380,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   }
   const int oy = WALLS ? min(y, ny + 2) : wrapi(y, ny);
   const int own = (oy + 3) * nx + wrapi(x, nx);
+  // byte offsets within a plane, for the buffer accesses
+  constexpr int RB = (int)sizeof(Real);
+  const uint32_t pbytes = (uint32_t)ps * RB;
+  const uint32_t cbytes = (uint32_t)nx * (uint32_t)ny * 8u;
+  int soffb[SLOTS], moffb[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    soffb[s] = soff[s] * RB;
+    moffb[s] = moff[s] * 8;
+  }
+  const int ownb = own * RB;
 
-  // no __restrict__: in the last RK stage f^n and f_dst are the same array
-  // (each node's f^n is read before its f_dst is written, by the same thread)
+  // Pointer views of the source array and the carried fields, for the
+  // specular-x loads (the other accesses go through buffer resources).  No
+  // __restrict__ anywhere: in the last RK stage f^n and f_dst are the same
+  // array (each node's f^n is read before its f_dst is written, by the same
+  // thread).
   const gmem<const Real>* src = as_global(reinterpret_cast<const Real*>(a.fsrc));
   const gmem<const Real>* fnp = as_global(reinterpret_cast<const Real*>(a.fn));
   gmem<Real>* dst = as_global(reinterpret_cast<Real*>(a.fdst));
@@ -367,6 +415,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     if (!XSPEC) return o;
     return xfl[s] ? (int64_t)(5 * (k / 5) + 4 - k % 5) * ps + soff[s] : o;
   };
+  // value of population k at tile slot s of the source array (specular x
+  // planes pick the plane per lane: pointer form)
+  auto ld_src = [&](int k, int s) -> Real {
+    if constexpr (XSPEC) return src[pl_off(k, s)];
+    else return bload<Real>(plane_rsrc(a.fsrc, k, pbytes), soffb[s]);
+  };
   // FN: the stage has an RK base term A f^n (A != 0); a template parameter so
   // that the load counts the waits below rely on are known at compile time
   constexpr bool use_fn = FN;
@@ -380,24 +434,30 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
 #pragma unroll
   for (int j = 0; j < G; ++j)
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) pre0[j][s] = src[pl_off(tile_pop(j), s)];
+    for (int s = 0; s < SLOTS; ++s) pre0[j][s] = ld_src(tile_pop(j), s);
   __builtin_amdgcn_sched_barrier(0);
   double cn_in[SLOTS], cp_in[SLOTS];
   {
     const int64_t N = (int64_t)nx * ny;
+    const __amdgpu_buffer_rsrc_t rn = plane_rsrc(a.cin, 0, cbytes), rp = plane_rsrc(a.cin, 1, cbytes);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-      cn_in[s] = cin[moff[s]];
-      cp_in[s] = cin[N + moff[s]];
+      if constexpr (XSPEC) {
+        cn_in[s] = cin[moff[s]];
+        cp_in[s] = cin[N + moff[s]];
+      } else {
+        cn_in[s] = bload<double>(rn, moffb[s]);
+        cp_in[s] = bload<double>(rp, moffb[s]);
+      }
     }
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int t = G; t < G + PF; ++t)
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[pl_off(tile_pop(t), s)];
+    for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = ld_src(tile_pop(t), s);
   // population 12 (p = 0 on both axes) needs no halo: read its own value
-  const Real f12 = src[12 * ps + own];
+  const Real f12 = XSPEC ? src[12 * ps + own] : bload<Real>(plane_rsrc(a.fsrc, 12, pbytes), ownb);
 
   auto plane = [&](int t) { return pl0 + (t % NB) * TN; };
 #pragma unroll
@@ -469,7 +529,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   __builtin_amdgcn_sched_barrier(0);
   Real fnv[25];
 #pragma unroll
-  for (int k = 0; k < 25; ++k) fnv[k] = use_fn ? fnp[k * ps + own] : (Real)0;
+  for (int k = 0; k < 25; ++k)
+    fnv[k] = !use_fn ? (Real)0 : XSPEC ? fnp[k * ps + own] : bload<Real>(plane_rsrc(a.fn, k, pbytes), ownb);
 
   // stage the second group and refill the ring behind it
 #pragma unroll
@@ -482,7 +543,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     }
     if (t + PF < 24) {
 #pragma unroll
-      for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[pl_off(tile_pop(t + PF), s)];
+      for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = ld_src(tile_pop(t + PF), s);
     }
   }
   // carried n and Delta p of f_src, tile + halo, into LDS
@@ -616,7 +677,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
         }
         if (t + PF < 24) {
 #pragma unroll
-          for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = src[pl_off(tile_pop(t + PF), s)];
+          for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = ld_src(tile_pop(t + PF), s);
         }
       }
     }
@@ -684,7 +745,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       out = (Real)__builtin_fmaf(px[kx], by[ky], __builtin_fmaf(qx[kx], hy_w[ky], (float)acc[k]));
     else
       out = acc[k] + (Real)(cfe * (sn * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky]))));
-    if (active) dst[k * ps + own] = out;
+    if (active) {
+      if constexpr (XSPEC) dst[k * ps + own] = out;
+      else bstore<Real>(out, plane_rsrc(a.fdst, k, pbytes), ownb);
+    }
     carry_add(k, (double)out, dn, djx, djy, de);
   }
 
@@ -693,8 +757,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     carry_finish<F32>(dn, djx, djy, de, a.rho0, a.tref, a.a, a.b, cn, cdp);
     const int64_t N = (int64_t)nx * ny;
     const int m = y * nx + x;
-    cout[m] = cn;
-    cout[N + m] = cdp;
+    if constexpr (XSPEC) {
+      cout[m] = cn;
+      cout[N + m] = cdp;
+    } else {
+      bstore<double>(cn, plane_rsrc(a.cout, 0, cbytes), m * 8);
+      bstore<double>(cdp, plane_rsrc(a.cout, 1, cbytes), m * 8);
+    }
     if (!(fabs(cn) < INFINITY)) a.flag[0] = 1;
   }
 }

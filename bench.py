@@ -757,7 +757,8 @@ def main():
     ap.add_argument("--workload", default="wave2048", choices=sorted(WORKLOADS))
     ap.add_argument("--graph", type=int, default=10, help="RK3 steps per HIP graph (batches)")
     ap.add_argument("--autotune", action="store_true", help="pick the tile height by trial (batches)")
-    ap.add_argument("--tile", type=int, default=8, choices=[8, 16])
+    ap.add_argument("--tile", type=int, default=8, choices=[8, 12, 16])
+    ap.add_argument("--strip", type=int, default=None, help="tile order: strip width in tiles (0 = rows)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="stepping time of each CPU-baseline leg (the oracle on all threads, then one)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -854,6 +855,8 @@ def main():
     else:
         lat = olb.Lattice(cases[0].params, device="cuda:0")
         lat.set_tile(args.tile)
+        if args.strip is not None:
+            lat.set_tile_order(args.strip)
         lat.set_base_temperature(float(np.mean(cases[0].T)))
         lat.set_fields(*cases[0].fields)
         n_stage, n_walls = lat.launch_counts()

@@ -138,8 +138,9 @@ olb_status olb_set_f(olb_ctx* c, const double* f);
  * OLB_E_STATE without walls.  Synchronous. */
 olb_status olb_wall_density(olb_ctx* c, double* nw_lo, double* nw_hi);
 
-/* Block height of the stage kernel: 8 (default) or 16 waves per workgroup;
- * each workgroup updates 63 x by nodes.  Results do not depend on it. */
+/* Block height of the stage kernel: 8 (default) or 16 waves per workgroup,
+ * or 12 with FP32 storage (OLB_E_ARG otherwise); each workgroup updates
+ * 63 x by nodes.  Results do not depend on it. */
 olb_status olb_set_tile(olb_ctx* c, int32_t by);
 /* FP32 departure storage keeps f - rho_ref b_kx b_ky, with the per-axis base
  * b = w (1 + h(0, T - 1)) of the equilibrium at rest and temperature T
@@ -197,12 +198,21 @@ olb_status olb_batch_set_tile(olb_batch* b, int32_t by);
 /* olb_set_base_temperature for instance i of the batch. */
 olb_status olb_batch_set_base_temperature(olb_batch* b, int32_t i, double T);
 olb_status olb_batch_set_tile_order(olb_batch* b, int32_t strip);
-/* Choose the stage tile height (8 or 16) by timing trial_steps steps of each
- * on a uniform rest state of every instance; the choice is read from / added
- * to the JSON file cache_path (NULL: no cache).  The trial overwrites the
- * instances: set their fields afterwards.  chosen_by may be NULL. */
+/* Choose the launch configuration by timing trial_steps RK-3 steps of each
+ * candidate on a uniform rest state of every instance, one parameter at a
+ * time: the stage tile height (8, 16; also 12 with FP32 storage), then the
+ * tile order (olb_batch_set_tile_order: rows, strips of 4, 8, 16), then,
+ * when the batch replays HIP graphs (olb_batch_use_graph), the RK-3 steps
+ * per graph (2, 10, 30).  None of them changes the results.  The choice is
+ * read from / added to the JSON file cache_path (NULL: no cache), keyed by
+ * precision, boundary kinds, instance count, total nodes and whether graphs
+ * are used.  The trial overwrites the instances: set their fields
+ * afterwards.  chosen_by (tile height) may be NULL. */
 olb_status olb_batch_autotune(olb_batch* b, int32_t trial_steps, const char* cache_path,
                               int32_t* chosen_by);
+/* The current launch configuration: tile height, tile order (strip width,
+ * 0 = rows) and RK-3 steps per graph (0 = direct launches). */
+olb_status olb_batch_launch_config(const olb_batch* b, int32_t* by, int32_t* strip, int32_t* steps_per_graph);
 /* Tiles per stage launch and the current tile height. */
 olb_status olb_batch_tiles(const olb_batch* b, int32_t* tiles, int32_t* by);
 const char* olb_batch_last_error(const olb_batch* b);

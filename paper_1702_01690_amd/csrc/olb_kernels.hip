@@ -1074,6 +1074,7 @@ hipError_t launch_stage(const BatchArgs& a, int real_bytes, int by, bool walls, 
     if (by == 8) return stage_x<double, 8>(a, walls, xspec, grid, s);
   } else {
     if (by == 16) return stage_x<float, 16>(a, walls, xspec, grid, s);
+    if (by == 12) return stage_x<float, 12>(a, walls, xspec, grid, s);
     if (by == 8) return stage_x<float, 8>(a, walls, xspec, grid, s);
   }
   return hipErrorInvalidValue;

@@ -471,7 +471,10 @@ struct Engine {
   }
 
   olb_status set_tile(int32_t b) {
-    if (b != 8 && b != 16) return fail(OLB_E_ARG, "tile height must be 8 or 16");
+    // 12 only with FP32 storage: two 12-wave workgroups per CU fit its
+    // 80-register budget, while FP64 (128 registers) would run one
+    if (b != 8 && b != 16 && !(b == 12 && rb == 4))
+      return fail(OLB_E_ARG, "tile height must be 8 or 16 (or 12 with FP32 storage)");
     if (b == by) return OLB_OK;
     by = b;
     return upload_desc();
@@ -507,27 +510,43 @@ struct Engine {
     for (const auto& q : p) nodes += (long long)q.nx * q.ny;
     std::ostringstream k;
     k << (rb == 8 ? "fp64" : "fp32") << (walls ? "-walls" : "-periodic") << (xspec ? "-xspec" : "") << "-n" << count()
-      << "-nodes" << nodes;
+      << "-nodes" << nodes << (graph_steps > 0 ? "-graphs" : "-direct");
     return k.str();
   }
 
-  static bool read_cache(const char* path, const std::string& key, int& b) {
+  // A tuned launch configuration: tile height, tile order (strip width) and
+  // RK-3 steps per graph (0 when the batch launches directly).
+  struct Tuning {
+    int by = 8, strip = 8, graph = 0;
+  };
+
+  static bool read_int(const std::string& text, size_t from, const char* field, int& v) {
+    const size_t at = text.find(std::string("\"") + field + "\":", from);
+    if (at == std::string::npos) return false;
+    v = std::atoi(text.c_str() + at + std::strlen(field) + 3);
+    return true;
+  }
+
+  bool read_cache(const char* path, const std::string& key, Tuning& t) const {
     if (!path) return false;
     std::ifstream in(path);
     if (!in) return false;
     std::stringstream ss;
     ss << in.rdbuf();
     const std::string text = ss.str();
-    const std::string pat = "\"" + key + "\"";
-    size_t at = text.find(pat);
+    const size_t at = text.find("\"" + key + "\"");
     if (at == std::string::npos) return false;
-    at = text.find("\"by\":", at);
-    if (at == std::string::npos) return false;
-    b = std::atoi(text.c_str() + at + 5);
-    return b == 8 || b == 16;
+    Tuning c;
+    if (!read_int(text, at, "by", c.by) || !read_int(text, at, "strip", c.strip) ||
+        !read_int(text, at, "graph", c.graph))
+      return false;
+    const bool by_ok = c.by == 8 || c.by == 16 || (c.by == 12 && rb == 4);
+    if (!by_ok || c.strip < 0 || c.strip > 1024 || c.graph < 0 || (c.graph > 0) != (graph_steps > 0)) return false;
+    t = c;
+    return true;
   }
 
-  static void write_cache(const char* path, const std::string& key, int b, const double ms[2]) {
+  static void write_cache(const char* path, const std::string& key, const Tuning& t, const std::string& trials) {
     if (!path) return;
     // keep other keys: naive merge by rewriting the object
     std::string body;
@@ -540,8 +559,8 @@ struct Engine {
       }
     }
     std::ostringstream entry;
-    entry << "\"" << key << "\": {\"by\": " << b << ", \"ms_per_step_by8\": " << ms[0]
-          << ", \"ms_per_step_by16\": " << ms[1] << "}";
+    entry << "\"" << key << "\": {\"by\": " << t.by << ", \"strip\": " << t.strip << ", \"graph\": " << t.graph
+          << ", \"ms_per_step\": {" << trials << "}}";
     std::string out;
     const size_t open = body.find('{'), close = body.rfind('}');
     if (open == std::string::npos || close == std::string::npos || body.find("\"" + key + "\"") != std::string::npos) {
@@ -556,47 +575,133 @@ struct Engine {
     o << out;
   }
 
+  olb_status apply_tuning(const Tuning& t) {
+    olb_status s = set_tile(t.by);
+    if (!s) s = set_tile_order(t.strip);
+    if (s) return s;
+    if (t.graph != graph_steps) {
+      drop_graph();
+      graph_steps = t.graph;
+    }
+    return OLB_OK;
+  }
+
+  // ms per RK-3 step of the current configuration, continuing from the
+  // uniform rest state autotune set up (a fixed point of the update): two
+  // untimed steps (or one graph, captured), then trial_steps rounded up to an
+  // even count (or to whole graphs) timed.  Even counts keep the carry index
+  // at 0, where graph replays start.
+  olb_status trial(int32_t trial_steps, hipEvent_t e0, hipEvent_t e1, double& ms) {
+    const int32_t warm = graph_steps > 0 ? graph_steps : 2;
+    const int32_t timed = graph_steps > 0 ? graph_steps * ((trial_steps + graph_steps - 1) / graph_steps)
+                                          : 2 * ((trial_steps + 1) / 2);
+    olb_status s = step(warm);
+    if (!s) s = hip(hipEventRecord(e0, stream), "event record");
+    if (!s) s = step(timed);
+    if (!s) s = hip(hipEventRecord(e1, stream), "event record");
+    if (!s) s = hip(hipEventSynchronize(e1), "event sync");
+    float t = 0.0f;
+    if (!s) s = hip(hipEventElapsedTime(&t, e0, e1), "event time");
+    ms = (double)t / timed;
+    return s;
+  }
+
+  // Search, one parameter at a time: the tile height (8, 16, and 12 with FP32
+  // storage) in the default order, then the tile order (rows, strips of 4, 8
+  // and 16 tiles) at the best height, then, when the batch replays graphs,
+  // the steps per graph (2, 10, 30).  Results do not depend on any of them.
   olb_status autotune(int32_t trial_steps, const char* cache_path, int32_t* chosen) {
     if (trial_steps < 1) return fail(OLB_E_ARG, "trial_steps must be >= 1");
     const std::string key = tune_key();
-    int best = 0;
+    Tuning best;
     if (read_cache(cache_path, key, best)) {
-      olb_status s = set_tile(best);
+      olb_status s = apply_tuning(best);
       if (s) return s;
-      if (chosen) *chosen = best;
+      if (chosen) *chosen = best.by;
       return OLB_OK;
     }
-    double ms[2] = {0.0, 0.0};
-    const int cand[2] = {8, 16};
-    const int saved_graph = graph_steps;
-    graph_steps = 0;
+    const bool graphs = graph_steps > 0;
+    best.graph = graph_steps;
     hipEvent_t e0, e1;
     olb_status s = hip(hipEventCreate(&e0), "event");
     if (s) return s;
     s = hip(hipEventCreate(&e1), "event");
-    if (s) return s;
-    for (int c = 0; c < 2 && !s; ++c) {
-      s = set_tile(cand[c]);
-      if (!s) s = fill_rest_state();
-      if (!s) s = step(1);
-      if (!s) s = hip(hipEventRecord(e0, stream), "event record");
-      if (!s) s = step(trial_steps);
-      if (!s) s = hip(hipEventRecord(e1, stream), "event record");
-      if (!s) s = hip(hipEventSynchronize(e1), "event sync");
-      float t = 0.0f;
-      if (!s) s = hip(hipEventElapsedTime(&t, e0, e1), "event time");
-      ms[c] = t / trial_steps;
+    if (s) {
+      (void)hipEventDestroy(e0);
+      return s;
+    }
+    // one rest state for all trials (every instance re-initialised, into
+    // carry 0)
+    cur = 0;
+    s = fill_rest_state();
+    std::ostringstream trials;
+    auto run = [&](const Tuning& t, const char* label, double& ms) {
+      olb_status r = apply_tuning(t);
+      if (!r) r = trial(trial_steps, e0, e1, ms);
+      if (!r) {
+        if (trials.tellp() > 0) trials << ", ";
+        trials << "\"" << label << "\": " << ms;
+      }
+      return r;
+    };
+    // direct launches while the height and order are chosen
+    Tuning t = best;
+    t.graph = 0;
+    double best_ms = 1e300;
+    const int heights[3] = {8, 16, 12};
+    for (int h = 0; h < (rb == 4 ? 3 : 2) && !s; ++h) {
+      t.by = heights[h];
+      t.strip = 8;
+      double ms = 0.0;
+      const std::string label = "by" + std::to_string(t.by);
+      s = run(t, label.c_str(), ms);
+      if (!s && ms < best_ms) {
+        best_ms = ms;
+        best.by = t.by;
+      }
+    }
+    t.by = best.by;
+    best_ms = 1e300;
+    const int strips[4] = {8, 0, 4, 16};
+    for (int w = 0; w < 4 && !s; ++w) {
+      t.strip = strips[w];
+      double ms = 0.0;
+      const std::string label = "by" + std::to_string(t.by) + "-strip" + std::to_string(t.strip);
+      s = run(t, label.c_str(), ms);
+      if (!s && ms < best_ms) {
+        best_ms = ms;
+        best.strip = t.strip;
+      }
+    }
+    if (graphs) {
+      t.strip = best.strip;
+      best_ms = 1e300;
+      const int lengths[3] = {10, 2, 30};
+      for (int g = 0; g < 3 && !s; ++g) {
+        t.graph = lengths[g];
+        double ms = 0.0;
+        const std::string label = "graph" + std::to_string(t.graph);
+        s = run(t, label.c_str(), ms);
+        if (!s && ms < best_ms) {
+          best_ms = ms;
+          best.graph = t.graph;
+        }
+      }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    graph_steps = saved_graph;
     for (int i = 0; i < count(); ++i) have_f[i] = false;  // trial states are discarded
+    cur = 0;
+    if (s) {
+      Tuning keep;
+      keep.graph = graphs ? best.graph : 0;
+      (void)apply_tuning(keep);
+      return s;
+    }
+    s = apply_tuning(best);
     if (s) return s;
-    best = ms[0] <= ms[1] ? 8 : 16;
-    s = set_tile(best);
-    if (s) return s;
-    write_cache(cache_path, key, best, ms);
-    if (chosen) *chosen = best;
+    write_cache(cache_path, key, best, trials.str());
+    if (chosen) *chosen = best.by;
     return OLB_OK;
   }
 
@@ -776,6 +881,13 @@ olb_status olb_batch_set_tile_order(olb_batch* b, int32_t strip) {
 olb_status olb_batch_autotune(olb_batch* b, int32_t trial_steps, const char* cache_path,
                               int32_t* chosen_by) {
   return b ? b->e.autotune(trial_steps, cache_path, chosen_by) : OLB_E_ARG;
+}
+olb_status olb_batch_launch_config(const olb_batch* b, int32_t* by, int32_t* strip, int32_t* steps_per_graph) {
+  if (!b || !by || !strip || !steps_per_graph) return OLB_E_ARG;
+  *by = b->e.by;
+  *strip = b->e.strip;
+  *steps_per_graph = b->e.graph_steps;
+  return OLB_OK;
 }
 olb_status olb_batch_tiles(const olb_batch* b, int32_t* tiles, int32_t* by) {
   if (!b || !tiles || !by) return OLB_E_ARG;

@@ -85,6 +85,7 @@ _SIGS = {
     "olb_batch_set_base_temperature": ([_vp, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
     "olb_batch_autotune": ([_vp, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "olb_batch_tiles": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "olb_batch_launch_config": ([_vp] + [ctypes.POINTER(ctypes.c_int32)] * 3, ctypes.c_int),
     "olb_batch_last_error": ([_vp], ctypes.c_char_p),
     "olb_batch_free": ([_vp], None),
     "olb_set_fields_device": ([_vp, _vp], ctypes.c_int),
@@ -401,6 +402,12 @@ def olb_batch_autotune(h, trial_steps, cache_path=None):
     return chosen.value
 
 
+def olb_batch_launch_config(h):
+    by, strip, graph = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().olb_batch_launch_config(h, ctypes.byref(by), ctypes.byref(strip), ctypes.byref(graph)), h, True)
+    return by.value, strip.value, graph.value
+
+
 def olb_batch_tiles(h):
     t, b = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().olb_batch_tiles(h, ctypes.byref(t), ctypes.byref(b)), h, True)
@@ -498,6 +505,10 @@ class Batch:
 
     def tiles(self):
         return olb_batch_tiles(self.h)
+
+    def launch_config(self):
+        """(tile height, strip width, RK-3 steps per graph)."""
+        return olb_batch_launch_config(self.h)
 
 
 # ------------------------------------------------------------------ closure --

@@ -136,30 +136,44 @@ def test_batch_tile_order_does_not_change_results():
         np.testing.assert_array_equal(a.get_f(i), b.get_f(i))
 
 
-def test_autotune_picks_a_tile_and_caches_it(tmp_path):
+@pytest.mark.parametrize("precision,graph", [(0, 0), (1, 2)])
+def test_autotune_picks_a_launch_configuration_and_caches_it(tmp_path, precision, graph):
+    """The autotuner's search (tile height, tile order, steps per graph) picks
+    a valid configuration, caches it, reads it back for a batch of the same
+    shape, and leaves the results bitwise those of the default
+    configuration."""
     olb = _olb()
-    cases = _channels()
+    cases = _channels(precision=precision)
     cache = str(tmp_path / "tune.json")
     b = olb.Batch([c.params for c in cases])
+    if graph:
+        b.use_graph(graph)
     by = b.autotune(trial_steps=2, cache_path=cache)
-    assert by in (8, 16)
+    cfg = b.launch_config()
+    print(f"[batch] autotune precision={precision} graph={graph}: {cfg}", flush=True)
+    assert by == cfg[0] and by in ((8, 12, 16) if precision else (8, 16))
+    assert cfg[1] in (0, 4, 8, 16)
+    assert cfg[2] == 0 if not graph else cfg[2] in (2, 10, 30)
     data = json.load(open(cache))
-    key = next(iter(data))
-    assert data[key]["by"] == by and data[key]["ms_per_step_by8"] > 0
+    entry = next(iter(data.values()))
+    assert (entry["by"], entry["strip"], entry["graph"]) == cfg and len(entry["ms_per_step"]) >= 6
     # the trial discarded the state: stepping now is an error
     with pytest.raises(olb.OlbError) as e:
         b.step(1)
     assert e.value.code == olb.OLB_E_STATE
     # a second batch of the same shape reads the cache
     b2 = olb.Batch([c.params for c in cases])
+    if graph:
+        b2.use_graph(graph)
     assert b2.autotune(trial_steps=2, cache_path=cache) == by
-    assert b2.tiles()[1] == by
+    assert b2.launch_config() == cfg
     for i, c in enumerate(cases):
         b.set_fields(i, *c.fields)
-    b.step(5)
-    ref = _batch(cases, by=by)
-    ref.step(5)
-    np.testing.assert_array_equal(b.get_f(0), ref.get_f(0))
+    b.step(6)
+    ref = _batch(cases)
+    ref.step(6)
+    for i in range(len(cases)):
+        np.testing.assert_array_equal(b.get_f(i), ref.get_f(i))
 
 
 def test_batch_fp32_per_instance_bases_equal_single_instance_runs_bitwise():

@@ -317,14 +317,18 @@ def test_fp32_spinodal4096_full_size_equals_tiled_crop(tbase):
 @pytest.mark.parametrize("name,precision", [("noisy70x37", 0), ("noisy70x37", 1), ("box70x37", 0),
                                             ("box70x37", 1)])
 def test_tile_height_does_not_change_results(name, precision):
-    """63 x 16 and 63 x 8 tiles give the same bits: a face reconstructed as a
-    tile's top face equals the one the tile above reconstructs as its lower
-    face (periodic and specular-box lattices, both storage precisions)."""
+    """63 x 16, 63 x 12 (FP32 storage) and 63 x 8 tiles give the same bits: a
+    face reconstructed as a tile's top face equals the one the tile above
+    reconstructs as its lower face (periodic and specular-box lattices, both
+    storage precisions)."""
     case = CASES[name]()
     print(f"[parity] tile height {name} precision={precision}", flush=True)
     a, fa, _ = run_gpu(case, 10, precision=precision, by=16)
     b, fb, _ = run_gpu(case, 10, precision=precision, by=8)
     np.testing.assert_array_equal(fa, fb)
+    if precision == 1:
+        c, fc, _ = run_gpu(case, 10, precision=precision, by=12)
+        np.testing.assert_array_equal(fc, fb)
 
 
 @pytest.mark.parametrize("precision", [0, 1])

@@ -22,7 +22,8 @@ def test_stage_kernels_fully_unrolled(tmp_path):
     subprocess.run(cmd, check=True, capture_output=True, timeout=900)
     lines = out.read_text().split("\n")
     starts = [i for i, l in enumerate(lines) if re.match(r"^_ZN4olbk12stage_kernelI\w+:", l)]
-    assert len(starts) == 32          # {FP64, FP32} x BY {8, 16} x walls x FN x specular x
+    # {FP64 BY 8, 16; FP32 BY 8, 12, 16} x walls x FN x specular x
+    assert len(starts) == 40
     for i in starts:
         name = lines[i].split(":")[0]
         body = []
@@ -34,5 +35,5 @@ def test_stage_kernels_fully_unrolled(tmp_path):
         scratch = sum(1 for l in body if l.startswith("scratch_"))
         # one barrier before the force stencils and one per streamed population
         assert barriers == 25, (name, barriers)
-        # at most a few spilled registers outside the loop, none at BY = 8
-        assert scratch <= (0 if "Li8E" in name else 8), (name, scratch)
+        # at most a few spilled registers outside the loop, none at BY = 8 or 12
+        assert scratch <= (0 if ("Li8E" in name or "Li12E" in name) else 8), (name, scratch)

@@ -3,16 +3,17 @@
 // A 3-layer convolutional network (3x3 kernels, periodic padding, 4 -> 32 ->
 // 32 -> 4 channels, ReLU between layers) maps the moments (n, u_x, u_y, T) of
 // a coarse lattice to a correction of those moments.  Every convolution is an
-// implicit GEMM on the bf16 matrix cores (v_mfma_f32_16x16x16_bf16, FP32
-// accumulate): forward, backward-data (fused with the ReLU mask) and
-// backward-weight (pixel reduction, FP32 atomics).  Master weights, Adam
+// implicit GEMM on the bf16 matrix cores with FP32 accumulation: forward
+// (v_mfma_f32_16x16x32_bf16, K steps of 32), backward-data (fused with the
+// ReLU mask) and backward-weight (pixel reduction, FP32 atomics) on
+// v_mfma_f32_16x16x16_bf16.  Master weights, Adam
 // moments and gradients are FP32; activations and gradients entering the
 // matrix cores are rounded to bf16 (round to nearest even).
 //
 // Layouts: activations [pixel][channel], pixel = y * nx + x; parameters are
 // one FP32 vector [W1 | b1 | W2 | b2 | W3 | b3] with W[co][ci][ky][kx];
 // bf16 weight matrices Wt[co][k] with k = tap * Cin + ci, tap = 3 ky + kx,
-// rows padded to 16 and k padded to a multiple of 16.
+// rows padded to 16 and k padded to a multiple of 32.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -31,6 +32,8 @@
 namespace olbk {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8s __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16;
 
@@ -59,12 +62,51 @@ __device__ __forceinline__ int nbr(Pix q, int tap, int nx, int ny) {
   return yy * nx + xx;
 }
 
-constexpr int kp_of(int cin) { return (9 * cin + 15) / 16 * 16; }
+// bf16 weight matrices Wt[co][k] have their rows padded to a multiple of 32
+// (the K step of the forward convolutions' matrix instruction)
+constexpr int kp_of(int cin) { return (9 * cin + 31) / 32 * 32; }
+
+// One forward K step (32 values of k = tap * CIN + ci) of the A operand of
+// v_mfma_f32_16x16x32_bf16: lane (i, g) holds A[i][8g .. 8g + 7], i.e. the
+// 8 consecutive k from k0 = 32 ks + 8g of its pixel.  With CIN a multiple of
+// 8 they share a tap (one 16-byte load); with CIN = 4 they span two taps.
+// at(tap, ci) is the address of channel ci of the tap's neighbour; k >= K
+// reads nothing and gives zeros.
+template <int CIN, typename At>
+__device__ __forceinline__ bf16x8 a_frag(int k0, int K, At at) {
+  bf16x8s v;
+  if constexpr (CIN % 8 == 0) {
+    if (k0 < K) {
+      const int tap = k0 / CIN, ci = k0 - tap * CIN;
+      const bf16* p = at(tap, ci);
+      const bf16x4 lo = *reinterpret_cast<const bf16x4*>(p), hi = *reinterpret_cast<const bf16x4*>(p + 4);
+      v = bf16x8s{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    } else {
+      v = bf16x8s{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+  } else {
+    static_assert(CIN == 4, "CIN: a multiple of 8, or 4");
+    bf16x4 h[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int k = k0 + 4 * j;
+      h[j] = k < K ? *reinterpret_cast<const bf16x4*>(at(k / 4, 0)) : bf16x4{0, 0, 0, 0};
+    }
+    v = bf16x8s{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+  }
+  return __builtin_bit_cast(bf16x8, v);
+}
+// B operand of the same step: lane (i, g) holds B[8g .. 8g + 7][i] = row i
+// of the weight block, 8 consecutive k (16-byte aligned)
+__device__ __forceinline__ bf16x8 b_frag(const bf16* row_k0) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const bf16x8s*>(row_k0));
+}
 
 // ---------------------------------------------------------------- forward --
 // Z[p][co] = b[co] + sum_k Wt[co][k] X[p + off(tap)][ci];  A = bf16(relu(Z)).
-// The bf16 weight matrix is staged in LDS once per workgroup (rows padded by 4
-// so that the 16 rows a fragment reads fall in different banks).  A wave
+// The bf16 weight matrix is staged in LDS once per workgroup (rows padded by 8
+// elements, so that every row starts 16-byte aligned for the fragments'
+// 16-byte reads).  A wave
 // computes FWD_MT tiles of 16 pixels x all output channels; for each tile all
 // activation loads are issued before its MFMAs (FWD_MT at most; fewer on small
 // lattices so that the grid still fills the chip).  STORE_Z keeps the FP32
@@ -75,12 +117,12 @@ template <int CIN, int COUT, bool RELU, bool STORE_Z, bool STORE_A>
 __global__ void __launch_bounds__(256) conv_fwd(const bf16* __restrict__ X, const bf16* __restrict__ Wt,
                                                 const float* __restrict__ bias, float* __restrict__ Z,
                                                 bf16* __restrict__ A, int nx, int ny, int mtw) {
-  constexpr int K = 9 * CIN, KP = kp_of(CIN), KS = KP / 16, NT = (COUT + 15) / 16, ROWS = 16 * NT;
-  constexpr int KL = KP + 4;  // LDS row stride (elements)
+  constexpr int K = 9 * CIN, KP = kp_of(CIN), KS = KP / 32, NT = (COUT + 15) / 16, ROWS = 16 * NT;
+  constexpr int KL = KP + 8;  // LDS row stride (elements): 16-byte aligned rows
   __shared__ __attribute__((aligned(16))) bf16 wl[ROWS * KL];
-  for (int e = threadIdx.x; e < ROWS * (KP / 4); e += 256) {
-    const int r = e / (KP / 4), c = e - r * (KP / 4);
-    *reinterpret_cast<bf16x4*>(wl + r * KL + 4 * c) = *reinterpret_cast<const bf16x4*>(Wt + (size_t)r * KP + 4 * c);
+  for (int e = threadIdx.x; e < ROWS * (KP / 8); e += 256) {
+    const int r = e / (KP / 8), c = e - r * (KP / 8);
+    *reinterpret_cast<bf16x8s*>(wl + r * KL + 8 * c) = *reinterpret_cast<const bf16x8s*>(Wt + (size_t)r * KP + 8 * c);
   }
   __syncthreads();
   const int P = nx * ny;
@@ -90,29 +132,19 @@ __global__ void __launch_bounds__(256) conv_fwd(const bf16* __restrict__ X, cons
     const int p0 = ((blockIdx.x * 4 + wave) * mtw + m) * 16;
     if (p0 >= P) break;  // wave-uniform; no barrier follows
     const Pix qa = pix_of(min(p0 + i, P - 1), nx);  // A-operand row (pixel)
-    bf16x4 a[KS];
+    auto at = [&](int tap, int ci) { return X + (size_t)nbr(qa, tap, nx, ny) * CIN + ci; };
+    bf16x8 a[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k0 = ks * 16 + 4 * g;  // 4 consecutive k share a tap (CIN % 4 == 0)
-      if (k0 < K) {
-        const int tap = k0 / CIN, ci = k0 - tap * CIN;
-        // 8-byte load: CIN and ci are multiples of 4, the buffers 256-aligned
-        a[ks] = *reinterpret_cast<const bf16x4*>(X + (size_t)nbr(qa, tap, nx, ny) * CIN + ci);
-      } else {
-        a[ks] = bf16x4{0, 0, 0, 0};
-      }
-    }
+    for (int ks = 0; ks < KS; ++ks) a[ks] = a_frag<CIN>(ks * 32 + 8 * g, K, at);
     f32x4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const int k0 = ks * 16 + 4 * g;
+      const int k0 = ks * 32 + 8 * g;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(wl + (t * 16 + i) * KL + k0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], b, acc[t], 0, 0, 0);
-      }
+      for (int t = 0; t < NT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], b_frag(wl + (t * 16 + i) * KL + k0), acc[t], 0, 0, 0);
     }
     // lane holds D[4g + v][i]: pixel p0 + 4g + v, channel t * 16 + i
 #pragma unroll
@@ -201,7 +233,7 @@ __global__ void __launch_bounds__(256) conv_bwd_data(const bf16* __restrict__ G,
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) conv_bwd_weight(const bf16* __restrict__ G, const bf16* __restrict__ X,
                                                        float* __restrict__ dW, int nx, int ny, int chunk) {
-  constexpr int K = 9 * CIN, KP = kp_of(CIN), MT = (COUT + 15) / 16, NTK = KP / 16;
+  constexpr int K = 9 * CIN, KP = (K + 15) / 16 * 16, MT = (COUT + 15) / 16, NTK = KP / 16;
   constexpr int TILES = MT * NTK;
   const int P = nx * ny;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -434,8 +466,8 @@ __global__ void delta_kernel(const float* __restrict__ Z3, int P, Norm nm, const
 // projection) are added to sums[4] when sums != nullptr.
 constexpr int FT = 16;            // output tile edge
 constexpr int R0 = FT + 6, R1 = FT + 4, R2 = FT + 2;
-// the current layer's weight matrix, rows padded by 4 (bank spread)
-constexpr int WL = kp_of(32) + 4;
+// the current layer's weight matrix, rows padded by 8 (16-byte aligned rows)
+constexpr int WL = kp_of(32) + 8;
 // hidden activations: 32 channels per pixel padded to 36, so that the 16
 // pixels one fragment reads start in 16 different bank pairs
 constexpr int HS = 36;
@@ -443,56 +475,66 @@ struct InferLds {
   bf16 x0[R0 * R0 * 4];
   bf16 a1[R1 * R1 * HS];
   bf16 a2[R2 * R2 * HS];
-  bf16 w[32 * WL];
+  __attribute__((aligned(16))) bf16 w[32 * WL];
   double part[8][4];
 };
 
-// copy a bf16 weight matrix (rows x KP) into LDS with row stride KP + 4
+// copy a bf16 weight matrix (rows x KP) into LDS with row stride KP + 8
 template <int ROWS, int KP>
 __device__ __forceinline__ void stage_weights(bf16* w, const bf16* __restrict__ Wt, int tid) {
-  for (int e = tid; e < ROWS * (KP / 4); e += 512) {
-    const int r = e / (KP / 4), c = e - r * (KP / 4);
-    *reinterpret_cast<bf16x4*>(w + r * (KP + 4) + 4 * c) = *reinterpret_cast<const bf16x4*>(Wt + (size_t)r * KP + 4 * c);
+  for (int e = tid; e < ROWS * (KP / 8); e += 512) {
+    const int r = e / (KP / 8), c = e - r * (KP / 8);
+    *reinterpret_cast<bf16x8s*>(w + r * (KP + 8) + 8 * c) = *reinterpret_cast<const bf16x8s*>(Wt + (size_t)r * KP + 8 * c);
   }
 }
 
 // MFMA layer on an R x R output region from an (R + 2) x (R + 2) input
-// region in LDS: m-tiles of 16 region pixels (row-major), spread over the
-// 8 waves.  Returns nothing; the epilogue functor gets (pixel, channel, z).
+// region in LDS: m-tiles of 16 region pixels (row-major), wave w taking
+// tiles w, w + 8, ...  The K steps run outermost: each weight fragment is
+// read from LDS once per wave and used for all of the wave's m-tiles (every
+// accumulator still sees its K steps in ascending order, as in conv_fwd).
+// The epilogue functor gets (pixel, channel, z).
 template <int CIN, int COUT, int R, int IS, typename Epi>
 __device__ __forceinline__ void lds_layer(const bf16* in, const bf16* w, const float* __restrict__ bias,
                                           int wave, int lane, Epi epi) {
-  constexpr int K = 9 * CIN, KP = kp_of(CIN), KS = KP / 16, NT = (COUT + 15) / 16;
-  constexpr int NPIX = R * R, MTILES = (NPIX + 15) / 16, RI = R + 2;
+  constexpr int K = 9 * CIN, KP = kp_of(CIN), KS = KP / 32, NT = (COUT + 15) / 16;
+  constexpr int NPIX = R * R, MTILES = (NPIX + 15) / 16, RI = R + 2, MW = (MTILES + 7) / 8;
   const int i = lane & 15, g = lane >> 4;
-  for (int mt = wave; mt < MTILES; mt += 8) {
-    const int j = min(mt * 16 + i, NPIX - 1);   // A-operand row: region pixel
+  int base[MW];  // this lane's A-operand row (region pixel) of each m-tile
+#pragma unroll
+  for (int m = 0; m < MW; ++m) {
+    const int j = min((wave + 8 * m) * 16 + i, NPIX - 1);
     const int r = j / R, c = j - r * R;
-    bf16x4 a[KS];
+    base[m] = (r * RI + c) * IS;
+  }
+  f32x4 acc[MW][NT];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k0 = ks * 16 + 4 * g;
-      if (k0 < K) {
-        const int tap = k0 / CIN, ci = k0 - tap * CIN;
+  for (int m = 0; m < MW; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k0 = ks * 32 + 8 * g;
+    bf16x8 b[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) b[t] = b_frag(w + (t * 16 + i) * (KP + 8) + k0);
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+      if (wave + 8 * m >= MTILES) continue;  // wave-uniform
+      auto at = [&](int tap, int ci) {
         const int ky = tap / 3, kx = tap - 3 * ky;
-        a[ks] = *reinterpret_cast<const bf16x4*>(in + ((r + ky) * RI + c + kx) * IS + ci);
-      } else {
-        a[ks] = bf16x4{0, 0, 0, 0};
-      }
+        return in + base[m] + (ky * RI + kx) * IS + ci;
+      };
+      const bf16x8 a = a_frag<CIN>(k0, K, at);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t], acc[m][t], 0, 0, 0);
     }
-    f32x4 acc[NT];
+  }
+  // lane holds D[4g + v][i]: region pixel mt*16 + 4g + v, channel t*16 + i
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k0 = ks * 16 + 4 * g;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(w + (t * 16 + i) * (KP + 4) + k0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ks], b, acc[t], 0, 0, 0);
-      }
-    }
-    // lane holds D[4g + v][i]: region pixel mt*16 + 4g + v, channel t*16 + i
+  for (int m = 0; m < MW; ++m) {
+    const int mt = wave + 8 * m;
+    if (mt >= MTILES) continue;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int co = t * 16 + i;
@@ -501,7 +543,7 @@ __device__ __forceinline__ void lds_layer(const bf16* in, const bf16* w, const f
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int q = mt * 16 + 4 * g + v;
-        if (q < NPIX) epi(q, co, acc[t][v] + bc);
+        if (q < NPIX) epi(q, co, acc[m][t][v] + bc);
       }
     }
   }

@@ -63,7 +63,10 @@ enum { OLB_BC_PERIODIC = 0, OLB_BC_DIFFUSE = 1, OLB_BC_SPECULAR_DIFFUSE = 2, OLB
 enum { OLB_FP64 = 0, OLB_FP32_MIXED = 1 };
 
 /* Problem statement of Secs. 2 and 3 of the paper:
- *   nx, ny      lattice nodes (frak N_1 x frak N_2).
+ *   nx, ny      lattice nodes (frak N_1 x frak N_2); (ny + 6) * nx * 8 must
+ *               stay below 2^31 (offsets within a distribution plane, with its
+ *               6 ghost rows, are 32-bit byte offsets), else OLB_E_ARG: up to
+ *               about 268 M nodes per instance, e.g. 16384 x 16377.
  *   ds, dt      lattice spacing and RK-3 time step (Eq. rk3).
  *   tau         BGK relaxation time (Eq. evolution), > 0.
  *   a, b        van der Waals EOS p^w = nT/(1 - bn) - a n^2 (Eq. vdw is

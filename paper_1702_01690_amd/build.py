@@ -1,4 +1,5 @@
-"""Build the gfx950 HIP library ``libolb.so`` in-tree with hipcc."""
+"""Build the gfx950 HIP library ``libolb.so`` and the measurement program
+``olb_probes`` in-tree with hipcc."""
 import os
 import subprocess
 import sys
@@ -7,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libolb.so")
+PROBES = os.path.join(HERE, "olb_probes")
 SOURCES = ["olb_kernels.hip", "olb_runtime.hip", "olb_closure.hip"]
 ARCH = os.environ.get("OLB_OFFLOAD_ARCH", "gfx950")
 
@@ -27,7 +29,20 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    build_probes(verbose)
     return LIB
+
+
+def build_probes(verbose: bool = False) -> str:
+    """The roofline probes (instruction issue costs, the stage kernel's memory
+    pattern without its arithmetic): a program of their own."""
+    flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
+    cmd = ["hipcc"] + flags + [os.path.join(CSRC, "olb_probes.hip"), "-o", PROBES + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(PROBES + ".tmp", PROBES)
+    return PROBES
 
 
 if __name__ == "__main__":

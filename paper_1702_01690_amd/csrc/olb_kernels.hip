@@ -136,18 +136,32 @@ __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, doub
 // offsets stay unscaled.  An indicator that underflows acts as a vanishing
 // one, which changes the result by far less than FP32 rounding (its three
 // values then agree to far below the rounding of f_i).
+//
+// Instruction forms (gfx950 issues two FP32 add / mul / FMA instructions per
+// SIMD quad-cycle when no operand sits in a scalar register, and one
+// ldexp / frexp / scalar-operand instruction): the outer differences are
+// formed with the opposite sign (e1 = -d1, e4 = -d4), so that 3 d2 - d1 and
+// 3 d3 - d4 are FMAs with a literal and no negated operand (3.0 is not an
+// inline constant, and the negated form would take it from a scalar
+// register); a3 enters squared only, so its sign is free.  The scale 2^-e is
+// assembled from the exponent field of the largest indicator by integer
+// arithmetic and applied by multiplication: for a normal m with biased
+// exponent E, m in [2^(E-127), 2^(E-126)), the factor 2^(126-E) puts m in
+// [1/2, 1).  Flipping signs and scaling by a power of two are exact, so the
+// result is the same as with d1, d4 and frexp / ldexp.  (m below the normal
+// range, i.e. differences of order 1e-19, is scaled by 2^126 only; the
+// weights are then those of values that agree far below FP32 rounding.)
 __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3, float v4) {
-  const float d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
-  const float a1 = d2 - d1, b1 = __builtin_fmaf(3.0f, d2, -d1);
+  const float e1 = v0 - v1, d2 = v2 - v1, d3 = v3 - v2, e4 = v3 - v4;
+  const float a1 = d2 + e1, b1 = __builtin_fmaf(3.0f, d2, e1);
   const float a2 = d3 - d2, b2 = d2 + d3;
-  const float a3 = d4 - d3, b3 = __builtin_fmaf(3.0f, d3, -d4);
+  const float a3 = d3 + e4, b3 = __builtin_fmaf(3.0f, d3, e4);
   const float t1 = __builtin_fmaf(a1 * (13.0f / 3.0f), a1, b1 * b1);
   const float t2 = __builtin_fmaf(a2 * (13.0f / 3.0f), a2, b2 * b2);
   const float t3 = __builtin_fmaf(a3 * (13.0f / 3.0f), a3, b3 * b3);
-  const int ne = -__builtin_amdgcn_frexp_expf(fmaxf(fmaxf(t1, t2), t3));
-  const float s1 = __builtin_amdgcn_ldexpf(t1, ne);
-  const float s2 = __builtin_amdgcn_ldexpf(t2, ne);
-  const float s3 = __builtin_amdgcn_ldexpf(t3, ne);
+  const float m = fmaxf(fmaxf(t1, t2), t3);
+  const float sc = __uint_as_float(0x7e800000u - (__float_as_uint(m) & 0x7f800000u));
+  const float s1 = t1 * sc, s2 = t2 * sc, s3 = t3 * sc;
   const float q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
   // 2^-126 in the second weight keeps den > 0 without a branch: den would
   // vanish only with two indicators zero, and then d2 = d3 = 0 (s1 = s2 = 0,
@@ -155,9 +169,9 @@ __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3
   // two weights vanish: num = 0 and the result is f_i, as the rule above
   // requires.  Elsewhere it moves den by 1e-37 at most.
   const float w1 = q2 * q3, w2 = __builtin_fmaf(q1, q3, 0x1p-126f), w3 = q1 * q2;
-  const float g1 = __builtin_fmaf(5.0f / 6.0f, d2, d1 * (-1.0f / 3.0f));
+  const float g1 = __builtin_fmaf(5.0f / 6.0f, d2, e1 * (1.0f / 3.0f));
   const float g2 = __builtin_fmaf(2.0f, d3, d2);
-  const float g3 = __builtin_fmaf(2.0f, d3, d4 * -0.5f);
+  const float g3 = __builtin_fmaf(2.0f, d3, e4 * 0.5f);
   const float num = __builtin_fmaf(w1, g1, __builtin_fmaf(w2, g2, w3 * g3));
   const float den = __builtin_fmaf(3.0f, w3, __builtin_fmaf(6.0f, w2, w1));
   return __builtin_fmaf(num, frcp(den), v2);

@@ -52,7 +52,12 @@ size_t head_bytes(int count) { return align_up((size_t)count * sizeof(olbk::Inst
 olb_status validate(const olb_params* p, std::string& why) {
   if (!p) { why = "null params"; return OLB_E_ARG; }
   if (p->nx < 1 || p->ny < 1) { why = "nx, ny must be >= 1"; return OLB_E_ARG; }
-  if ((int64_t)(p->ny + 6) * p->nx >= (int64_t)1 << 31) { why = "lattice too large"; return OLB_E_ARG; }
+  // plane and carried-field offsets are 32-bit byte offsets (buffer resources):
+  // an FP64 plane of (ny + 6) x nx values must stay below 2^31 bytes
+  if ((int64_t)(p->ny + 6) * p->nx * 8 >= (int64_t)1 << 31) {
+    why = "lattice too large: (ny + 6) * nx * 8 bytes must stay below 2^31";
+    return OLB_E_ARG;
+  }
   if (p->bc_x != OLB_BC_PERIODIC && p->bc_x != OLB_BC_SPECULAR) {
     why = "bc_x must be periodic or specular (walls are supported across y only)"; return OLB_E_ARG;
   }

@@ -54,11 +54,16 @@ def test_workspace_size_and_validation_codes():
              (dict(bc_x=1), olb.OLB_E_ARG), (dict(bc_x=2), olb.OLB_E_ARG), (dict(bc_x=3, nx=2), olb.OLB_E_ARG),
              (dict(bc_y=1, ny=2), olb.OLB_E_ARG),
              (dict(nx=0), olb.OLB_E_ARG), (dict(precision=1, rho_ref=0.0), olb.OLB_E_ARG),
-             (dict(bc_y=1, tw_lo=0.0), olb.OLB_E_DOMAIN), (dict(sigma=-1.0), olb.OLB_E_ARG)]
+             (dict(bc_y=1, tw_lo=0.0), olb.OLB_E_DOMAIN), (dict(sigma=-1.0), olb.OLB_E_ARG),
+             # 32-bit byte offsets within a plane: 16384 x 16384 (with its 6 ghost rows) is one
+             # plane too many for FP64 values, and the carried FP64 fields bound FP32 storage alike
+             (dict(nx=16384, ny=16384), olb.OLB_E_ARG), (dict(nx=16384, ny=16384, precision=1, rho_ref=1.0), olb.OLB_E_ARG)]
     for kw, code in cases:
         with pytest.raises(olb.OlbError) as e:
             olb.olb_workspace_bytes(_params(**kw))
         assert e.value.code == code, kw
+    # the largest accepted FP64 lattice of that width: (ny + 6) * 16384 * 8 < 2^31
+    assert olb.olb_workspace_bytes(_params(nx=16384, ny=16384 - 7)) > 0
 
 
 def test_init_rejects_small_or_misaligned_workspace_without_touching_device():

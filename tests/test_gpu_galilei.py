@@ -144,7 +144,17 @@ def test_moving_bubble():
             track.append(phase.track_bubble(n, T, c.extra["x"], c.extra["y"], V * t, c.extra["R0"],
                                             c.extra["xi"], 1.0))
         g0 = track[0][1] * track[0][3]
-        assert abs(track[0][0]) < 1e-8                # the bubble at rest stays on x = 0
+        # the bubble at rest stays on x = 0: the lattice (x_i = -x_{2N-1-i}) and the
+        # input are mirror-symmetric about x = 0, so its density field must stay so
+        # (only the left-to-right summation order of the stencils breaks the
+        # symmetry, at rounding level); the fitted centre is converged only to the
+        # least-squares step tolerance (about 1.5e-8 of the parameter vector)
+        n0 = b.moments(0)[0]
+        asym = float(np.max(np.abs(n0 - n0[:, ::-1]))) / (nl - ng)
+        print(f"[moving-bubble] t={t:.0f}: rest bubble mirror asymmetry {asym:.2e}, fitted centre "
+              f"{track[0][0]:+.2e}", flush=True)
+        assert asym < 1e-10
+        assert abs(track[0][0]) < 1e-6
         for (V, tr) in zip(speeds[1:], track[1:]):
             eps[V].append(abs(tr[1] * tr[3] / g0 - 1.0))
             lag[V] = tr[0] - V * t

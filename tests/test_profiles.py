@@ -33,5 +33,10 @@ def test_traffic_entry_is_consistent(workload):
     assert e["write_factor"] == pytest.approx(1.0, rel=1e-3)
     v = e["valu"]
     assert v["insts_per_launch"] > 0 and v["f64_flops_per_launch"] > 0
+    # dual issue: at most one extra instruction per issue quad-cycle
+    assert 0 <= v["dual_issue_quads_per_launch"] <= v["insts_per_launch"] / 2
+    # the profiled launches' clock: GPU-active cycles per XCD over the dispatch time
+    assert 0.5 < v["clock_ghz"] <= 2.4
+    assert v["gui_cycles_per_xcd"] == pytest.approx(v["clock_ghz"] * 1e9 * v["profiled_launch_s"], rel=5e-3)
     assert os.path.exists(os.path.join(ROOT, v["source"]))
     assert os.path.exists(os.path.join(ROOT, e["source"]))

@@ -14,7 +14,9 @@
 //                        library's storage order (25 planes) and tile order
 //                        (XCD-contiguous runs, strips of 8 tile columns), in
 //                        whole-row tile order, and with rows of the 25
-//                        populations interleaved; plus a plain device copy
+//                        populations interleaved; workgroups that march up
+//                        2, 4 or 8 tiles of a column and keep the 6 rows that
+//                        consecutive tiles share in LDS; a plain device copy
 //   olb_probes all       both
 //
 // Every access of the pattern kernels stays inside the arrays it addresses
@@ -260,6 +262,94 @@ __global__ void __launch_bounds__(NT) pattern_kernel(const double* src, const do
   }
 }
 
+// Marching: a workgroup takes MT vertically adjacent tiles of one tile column
+// in turn; per population it keeps the 6 rows the next tile shares (rows BY ..
+// BY + 5 of the region) in LDS and loads only the other BY rows of the next
+// region.  25 x 6 x 69 values of LDS (83 KB): one workgroup per CU.
+template <bool FN, int MT>
+__global__ void __launch_bounds__(NT) march_kernel(const double* src, const double* fn, double* dst,
+                                                   const double* cin, double* cout) {
+  constexpr int GY = TILES_Y / MT;                   // tile groups per column
+  constexpr int GROUPS = TILES_X * GY;
+  constexpr int NEW = TW * BY;                       // region values loaded after the first tile
+  extern __shared__ double lds[];
+  double* plane = lds;                               // [2][TN]
+  double* keep = lds + 2 * TN;                       // [25][6 * TW]
+  const int b = blockIdx.x;
+  const int g = (b & 7) * (GROUPS / 8) + (b >> 3);
+  const int per = 8 * GY;                            // strips of 8 tile columns, as the library
+  const int s = g / per;
+  const int w = min(8, TILES_X - s * 8);
+  const int r = g - s * per;
+  const int gy = r / w, tile_x = s * 8 + (r - gy * w);
+  const int x0 = tile_x * TILE_X;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  const bool active = tx < TILE_X && x0 + tx < NX;
+  const unsigned pbytes = (unsigned)(ROWS * NX * 8), cbytes = (unsigned)NX * NY * 8u;
+  auto pop = [&](const double* a, int k) { return rsrc(a + k * ROWS * NX, pbytes); };
+  for (int j = 0; j < MT; ++j) {
+    const int y0 = (gy * MT + j) * BY;
+    const int first = j == 0 ? 0 : 6 * TW;           // region index of the first value loaded
+    const int count = j == 0 ? TN : NEW;
+    int foff[SLOTS], coff[SLOTS], slot[SLOTS];
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+      const int i = tid + q * NT;
+      const int ri = first + min(i, count - 1);
+      const int rr = ri / TW, cc = ri - rr * TW;
+      foff[q] = ((wrap(y0 - 3 + rr, NY) + 3) * NX + wrap(x0 - 3 + cc, NX)) * 8;
+      slot[q] = i < count ? ri : -1;
+      const int ci = min(i, TN - 1), cr = ci / TW, ccc = ci - cr * TW;
+      coff[q] = (wrap(y0 - 3 + cr, NY) * NX + wrap(x0 - 3 + ccc, NX)) * 8;
+    }
+    const int xo = wrap(x0 + tx, NX), yo = y0 + ty;
+    const int own = ((yo + 3) * NX + xo) * 8, ownc = (yo * NX + xo) * 8;
+    double acc = 0.0;
+    {
+      const auto rn = rsrc(cin, cbytes), rp = rsrc(cin + (long long)NX * NY, cbytes);
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q) acc += ld(rn, coff[q]) + ld(rp, coff[q]);
+    }
+    double ring[PF][SLOTS];
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q) ring[k][q] = ld(pop(src, k), foff[q]);
+    double fnv[25];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) fnv[k] = FN ? ld(pop(fn, k), own) : 0.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+      double* pl = plane + (k & 1) * TN;
+      double* kp = keep + k * 6 * TW;
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q)
+        if (slot[q] >= 0) pl[slot[q]] = ring[k % PF][q];
+      if (j > 0)
+        for (int i = tid; i < 6 * TW; i += NT) pl[i] = kp[i];
+      if (k + PF < 25) {
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) ring[k % PF][q] = ld(pop(src, k + PF), foff[q]);
+      }
+      __syncthreads();
+      const double v = pl[(ty + 3) * TW + tx + 3] + pl[(ty + 3) * TW + tx] + pl[ty * TW + tx + 3] +
+                       pl[(ty + 6) * TW + tx + 3];
+      // rows BY .. BY + 5 for the next tile: read after this barrier, and kp is
+      // next read (for population k of the next tile) after further barriers
+      if (j + 1 < MT)
+        for (int i = tid; i < 6 * TW; i += NT) kp[i] = pl[BY * TW + i];
+      sum += v;
+      if (active) st(v + fnv[k] + (k == 0 ? acc : 0.0), pop(dst, k), own);
+    }
+    if (active) {
+      st(sum, rsrc(cout, cbytes), ownc);
+      st(0.5 * sum, rsrc(cout + (long long)NX * NY, cbytes), ownc);
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void copy_kernel(const double* __restrict__ a, double* __restrict__ b, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     b[i] = a[i];
@@ -301,6 +391,19 @@ void run_pattern() {
     rep(order, "rows interleaved", false, time_ms([&] { pattern_kernel<false, true><<<TILES, blk>>>(f0, f1, f2, c0, c1, strip); }, reps));
     rep(order, "rows interleaved", true, time_ms([&] { pattern_kernel<true, true><<<TILES, blk>>>(f0, f1, f2, c0, c1, strip); }, reps));
   }
+  const size_t lds = (size_t)(2 * TN + 25 * 6 * TW) * 8;
+  auto marching = [&](auto kern, int mt, bool fn) {
+    CK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    char order[64];
+    std::snprintf(order, sizeof order, "strips of 8, marching %d tiles", mt);
+    rep(order, "planes", fn, time_ms([&] { kern<<<TILES / mt, blk, lds>>>(f0, f1, f2, c0, c1); }, reps));
+  };
+  marching(march_kernel<false, 2>, 2, false);
+  marching(march_kernel<true, 2>, 2, true);
+  marching(march_kernel<false, 4>, 4, false);
+  marching(march_kernel<true, 4>, 4, true);
+  marching(march_kernel<false, 8>, 8, false);
+  marching(march_kernel<true, 8>, 8, true);
   CK(hipFree(f0));
   CK(hipFree(f1));
   CK(hipFree(f2));

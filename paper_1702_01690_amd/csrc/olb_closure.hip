@@ -96,6 +96,31 @@ __device__ __forceinline__ bf16x8 a_frag(int k0, int K, At at) {
   }
   return __builtin_bit_cast(bf16x8, v);
 }
+// The same fragment without branches, for LDS operands: with CIN a multiple
+// of 8 and K a multiple of 32 every k0 is below K; with CIN = 4 the reads
+// past K use tap 0 and are replaced by zeros.
+template <int CIN, typename At>
+__device__ __forceinline__ bf16x8 a_frag_sel(int k0, int K, At at) {
+  bf16x8s v;
+  if constexpr (CIN % 8 == 0) {
+    static_assert((9 * CIN) % 32 == 0, "K a multiple of the K step");
+    const int tap = k0 / CIN, ci = k0 - tap * CIN;
+    const bf16* p = at(tap, ci);
+    const bf16x4 lo = *reinterpret_cast<const bf16x4*>(p), hi = *reinterpret_cast<const bf16x4*>(p + 4);
+    v = bf16x8s{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  } else {
+    static_assert(CIN == 4, "CIN: a multiple of 8, or 4");
+    bf16x4 h[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int k = k0 + 4 * j;
+      const bf16x4 r = *reinterpret_cast<const bf16x4*>(at(k < K ? k / 4 : 0, 0));
+      h[j] = k < K ? r : bf16x4{0, 0, 0, 0};
+    }
+    v = bf16x8s{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+  }
+  return __builtin_bit_cast(bf16x8, v);
+}
 // B operand of the same step: lane (i, g) holds B[8g .. 8g + 7][i] = row i
 // of the weight block, 8 consecutive k (16-byte aligned)
 __device__ __forceinline__ bf16x8 b_frag(const bf16* row_k0) {
@@ -456,54 +481,75 @@ __global__ void delta_kernel(const float* __restrict__ Z3, int P, Norm nm, const
 }
 
 // ------------------------------------------------------- fused inference --
-// The whole network for one 16 x 16 output tile in one workgroup of 8 waves:
+// The whole network for 16 x 16 output tiles in one persistent workgroup of
+// IW waves per CU: the three bf16 weight matrices are staged in LDS once, then
+// the workgroup takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...  For each,
 // the normalised input on the 22 x 22 region around the tile, layer 1 on
 // 20 x 20, layer 2 on 18 x 18 and layer 3 on the tile itself, every
 // intermediate in LDS (the halo rows are recomputed by neighbouring tiles).
-// Same operands, instruction and k order as the layer-by-layer kernels, so
-// the network output is the same to the bit; only the moment planes and the
-// corrections touch HBM.  Channel sums of the output (for the conservative
-// projection) are added to sums[4] when sums != nullptr.
+// The next tile's input is loaded into registers while layer 2 runs and
+// written to LDS before its end (the input region is free once layer 1 is
+// done), so only two barriers separate the layers of a tile.  Same operands,
+// instruction and k order as the layer-by-layer kernels, so the network
+// output is the same to the bit; only the moment planes and the corrections
+// touch HBM.  Channel sums of the output (for the conservative projection)
+// are added to sums[4] when sums != nullptr.
 constexpr int FT = 16;            // output tile edge
 constexpr int R0 = FT + 6, R1 = FT + 4, R2 = FT + 2;
-// the current layer's weight matrix, rows padded by 8 (16-byte aligned rows)
-constexpr int WL = kp_of(32) + 8;
+// weight matrices, rows padded by 8 (16-byte aligned rows)
+constexpr int WL1 = kp_of(4) + 8, WL = kp_of(32) + 8;
 // hidden activations: 32 channels per pixel padded to 36, so that the 16
 // pixels one fragment reads start in 16 different bank pairs
 constexpr int HS = 36;
+// waves per inference workgroup
+constexpr int IW = 8;
 struct InferLds {
+  __attribute__((aligned(16))) bf16 w1[32 * WL1];
+  __attribute__((aligned(16))) bf16 w2[32 * WL];
+  __attribute__((aligned(16))) bf16 w3[16 * WL];
   bf16 x0[R0 * R0 * 4];
   bf16 a1[R1 * R1 * HS];
   bf16 a2[R2 * R2 * HS];
-  __attribute__((aligned(16))) bf16 w[32 * WL];
-  double part[8][4];
+  double part[IW][4];
 };
+static_assert(R0 * R0 <= 64 * IW, "one input pixel per thread");
 
 // copy a bf16 weight matrix (rows x KP) into LDS with row stride KP + 8
 template <int ROWS, int KP>
 __device__ __forceinline__ void stage_weights(bf16* w, const bf16* __restrict__ Wt, int tid) {
-  for (int e = tid; e < ROWS * (KP / 8); e += 512) {
+  for (int e = tid; e < ROWS * (KP / 8); e += 64 * IW) {
     const int r = e / (KP / 8), c = e - r * (KP / 8);
     *reinterpret_cast<bf16x8s*>(w + r * (KP + 8) + 8 * c) = *reinterpret_cast<const bf16x8s*>(Wt + (size_t)r * KP + 8 * c);
   }
 }
 
 // MFMA layer on an R x R output region from an (R + 2) x (R + 2) input
-// region in LDS: m-tiles of 16 region pixels (row-major), wave w taking
-// tiles w, w + 8, ...  The K steps run outermost: each weight fragment is
-// read from LDS once per wave and used for all of the wave's m-tiles (every
-// accumulator still sees its K steps in ascending order, as in conv_fwd).
-// The epilogue functor gets (pixel, channel, z).
+// region in LDS: m-tiles of 16 region pixels (row-major), wave w of the IW
+// waves taking tiles w, w + IW, ...  The product is taken transposed, weights as the A
+// operand and activations as the B operand, so that a lane receives four
+// consecutive output channels of one pixel (one 8-byte LDS store instead of
+// four 2-byte ones); each output is the same sum of the same exact bf16
+// products in the same K steps as in conv_fwd.  The K steps run outermost:
+// each weight fragment is read from LDS once per wave and used for all of
+// the wave's m-tiles (every accumulator still sees its K steps in ascending
+// order).  All fragments of a K step are read before its MFMAs, and a wave
+// with one m-tile fewer than the others computes its last one on a clamped
+// (valid) region pixel and discards it, so that a K step is one branch-free
+// block whose reads the compiler can move ahead of the previous step's
+// MFMAs.  `wave` must be uniform (readfirstlane).  The epilogue functor gets
+// (pixel, first channel co, the four values of channels co .. co + 3), for
+// co < COUT.
 template <int CIN, int COUT, int R, int IS, typename Epi>
 __device__ __forceinline__ void lds_layer(const bf16* in, const bf16* w, const float* __restrict__ bias,
                                           int wave, int lane, Epi epi) {
   constexpr int K = 9 * CIN, KP = kp_of(CIN), KS = KP / 32, NT = (COUT + 15) / 16;
-  constexpr int NPIX = R * R, MTILES = (NPIX + 15) / 16, RI = R + 2, MW = (MTILES + 7) / 8;
+  constexpr int NPIX = R * R, MTILES = (NPIX + 15) / 16, RI = R + 2, MW = (MTILES + IW - 1) / IW;
+  static_assert(COUT % 4 == 0, "four channels per lane");
   const int i = lane & 15, g = lane >> 4;
-  int base[MW];  // this lane's A-operand row (region pixel) of each m-tile
+  int base[MW];  // this lane's activation row (region pixel) of each m-tile
 #pragma unroll
   for (int m = 0; m < MW; ++m) {
-    const int j = min((wave + 8 * m) * 16 + i, NPIX - 1);
+    const int j = min((wave + IW * m) * 16 + i, NPIX - 1);
     const int r = j / R, c = j - r * R;
     base[m] = (r * RI + c) * IS;
   }
@@ -515,91 +561,117 @@ __device__ __forceinline__ void lds_layer(const bf16* in, const bf16* w, const f
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
     const int k0 = ks * 32 + 8 * g;
-    bf16x8 b[NT];
+    bf16x8 b[NT], a[MW];
 #pragma unroll
     for (int t = 0; t < NT; ++t) b[t] = b_frag(w + (t * 16 + i) * (KP + 8) + k0);
 #pragma unroll
     for (int m = 0; m < MW; ++m) {
-      if (wave + 8 * m >= MTILES) continue;  // wave-uniform
       auto at = [&](int tap, int ci) {
         const int ky = tap / 3, kx = tap - 3 * ky;
         return in + base[m] + (ky * RI + kx) * IS + ci;
       };
-      const bf16x8 a = a_frag<CIN>(k0, K, at);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t], acc[m][t], 0, 0, 0);
+      a[m] = a_frag_sel<CIN>(k0, K, at);
     }
+#pragma unroll
+    for (int m = 0; m < MW; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[t], a[m], acc[m][t], 0, 0, 0);
   }
-  // lane holds D[4g + v][i]: region pixel mt*16 + 4g + v, channel t*16 + i
+  // lane (i, g) holds the transposed D[4g + v][i]: channel t*16 + 4g + v of
+  // region pixel mt*16 + i
 #pragma unroll
   for (int m = 0; m < MW; ++m) {
-    const int mt = wave + 8 * m;
+    const int mt = wave + IW * m;
     if (mt >= MTILES) continue;
+    const int q = mt * 16 + i;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int co = t * 16 + i;
-      if (co >= COUT) continue;
-      const float bc = bias[co];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int q = mt * 16 + 4 * g + v;
-        if (q < NPIX) epi(q, co, acc[m][t][v] + bc);
-      }
+      const int co = t * 16 + 4 * g;
+      if (co >= COUT || q >= NPIX) continue;
+      epi(q, co, f32x4{acc[m][t][0] + bias[co], acc[m][t][1] + bias[co + 1], acc[m][t][2] + bias[co + 2],
+                       acc[m][t][3] + bias[co + 3]});
     }
   }
 }
 
-__global__ void __launch_bounds__(512) infer_kernel(const double* __restrict__ m, Norm nm,
+// four bf16 values of ReLU(z) as one 8-byte LDS store (dst 8-byte aligned)
+__device__ __forceinline__ void store_relu4(bf16* dst, f32x4 z) {
+  *reinterpret_cast<bf16x4*>(dst) = bf16x4{(short)to_bf16(fmaxf(z[0], 0.f)), (short)to_bf16(fmaxf(z[1], 0.f)),
+                                          (short)to_bf16(fmaxf(z[2], 0.f)), (short)to_bf16(fmaxf(z[3], 0.f))};
+}
+
+__global__ void __launch_bounds__(64 * IW) infer_kernel(const double* __restrict__ m, Norm nm,
                                                     const bf16* __restrict__ W1, const bf16* __restrict__ W2,
                                                     const bf16* __restrict__ W3, const float* __restrict__ b1,
                                                     const float* __restrict__ b2, const float* __restrict__ b3,
-                                                    int nx, int ny, int tiles_x, double* __restrict__ delta,
-                                                    double* __restrict__ sums) {
+                                                    int nx, int ny, int tiles_x, int ntiles,
+                                                    double* __restrict__ delta, double* __restrict__ sums) {
   __shared__ InferLds sm;
   const int P = nx * ny;
-  const int ty0 = (blockIdx.x / tiles_x) * FT, tx0 = (blockIdx.x % tiles_x) * FT;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // normalised input on the 22 x 22 region (periodic wrap)
-  for (int e = tid; e < R0 * R0; e += 512) {
-    const int r = e / R0, c = e - r * R0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // thread tid < 22 * 22 carries input pixel tid of the region: its four
+  // moments, loaded (periodic wrap) and then written normalised to LDS
+  double in[4];
+  auto load_input = [&](int tile) {
+    if (tid >= R0 * R0) return;
+    const int ty0 = (tile / tiles_x) * FT, tx0 = (tile % tiles_x) * FT;
+    const int r = tid / R0, c = tid - r * R0;
     int gy = (ty0 - 3 + r) % ny, gx = (tx0 - 3 + c) % nx;
     gy += gy < 0 ? ny : 0;
     gx += gx < 0 ? nx : 0;
     const size_t p = (size_t)gy * nx + gx;
 #pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-      sm.x0[e * 4 + ch] = to_bf16((float)((m[(size_t)ch * P + p] - nm.in_mean[ch]) * nm.in_inv_scale[ch]));
-  }
-  stage_weights<32, kp_of(4)>(sm.w, W1, tid);
-  __syncthreads();
-  lds_layer<4, 32, R1, 4>(sm.x0, sm.w, b1, wave, lane,
-                          [&](int q, int co, float z) { sm.a1[q * HS + co] = to_bf16(fmaxf(z, 0.f)); });
-  __syncthreads();
-  stage_weights<32, kp_of(32)>(sm.w, W2, tid);
-  __syncthreads();
-  lds_layer<32, 32, R2, HS>(sm.a1, sm.w, b2, wave, lane,
-                            [&](int q, int co, float z) { sm.a2[q * HS + co] = to_bf16(fmaxf(z, 0.f)); });
-  __syncthreads();
-  stage_weights<16, kp_of(32)>(sm.w, W3, tid);
-  __syncthreads();
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  lds_layer<32, 4, FT, HS>(sm.a2, sm.w, b3, wave, lane, [&](int q, int co, float z) {
-    const int r = q / FT, c = q - r * FT;
-    const int gy = ty0 + r, gx = tx0 + c;
-    if (gy < ny && gx < nx) {
-      delta[(size_t)co * P + (size_t)gy * nx + gx] = (double)z * (double)nm.out_scale[co];
+    for (int ch = 0; ch < 4; ++ch) in[ch] = m[(size_t)ch * P + p];
+  };
+  auto store_input = [&]() {
+    if (tid >= R0 * R0) return;
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (k == co) s[k] += (double)z;
-    }
-  });
+    for (int ch = 0; ch < 4; ++ch)
+      sm.x0[tid * 4 + ch] = to_bf16((float)((in[ch] - nm.in_mean[ch]) * nm.in_inv_scale[ch]));
+  };
+  int tile = blockIdx.x;
+  load_input(tile);
+  stage_weights<32, kp_of(4)>(sm.w1, W1, tid);
+  stage_weights<32, kp_of(32)>(sm.w2, W2, tid);
+  stage_weights<16, kp_of(32)>(sm.w3, W3, tid);
+  store_input();
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int ty0 = (tile / tiles_x) * FT, tx0 = (tile % tiles_x) * FT;
+    // the input region (and, on the first tile, the weights) are in LDS; a1
+    // was last read by the previous tile's layer 2, before its second barrier
+    __syncthreads();
+    lds_layer<4, 32, R1, 4>(sm.x0, sm.w1, b1, wave, lane,
+                            [&](int q, int co, f32x4 z) { store_relu4(sm.a1 + q * HS + co, z); });
+    // a1 complete; the input region is free (layer 2 writes a2, which the
+    // previous tile's layer 3 read before this tile's first barrier)
+    __syncthreads();
+    const int next = tile + gridDim.x;
+    if (next < ntiles) load_input(next);
+    lds_layer<32, 32, R2, HS>(sm.a1, sm.w2, b2, wave, lane,
+                              [&](int q, int co, f32x4 z) { store_relu4(sm.a2 + q * HS + co, z); });
+    if (next < ntiles) store_input();
+    __syncthreads();
+    lds_layer<32, 4, FT, HS>(sm.a2, sm.w3, b3, wave, lane, [&](int q, int, f32x4 z) {
+      const int r = q / FT, c = q - r * FT;
+      const int gy = ty0 + r, gx = tx0 + c;
+      if (gy < ny && gx < nx) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          delta[(size_t)k * P + (size_t)gy * nx + gx] = (double)z[k] * (double)nm.out_scale[k];
+          s[k] += (double)z[k];
+        }
+      }
+    });
+  }
   if (sums) {
-    // lanes hold channel (lane & 15): fold the four lane groups, then waves
+    // lanes 0..15 hold all four channels of their pixels (the others hold
+    // zeros): fold the 64 lanes, then the waves
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       double v = s[k];
-      v += __shfl_xor(v, 16);
-      v += __shfl_xor(v, 32);
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
       s[k] = v;
     }
     if (lane < 4) sm.part[wave][lane] = s[lane];
@@ -607,10 +679,20 @@ __global__ void __launch_bounds__(512) infer_kernel(const double* __restrict__ m
     if (tid < 4) {
       double t = 0.0;
 #pragma unroll
-      for (int w = 0; w < 8; ++w) t += sm.part[w][tid];
+      for (int w = 0; w < IW; ++w) t += sm.part[w][tid];
       atomicAdd(&sums[tid], t);
     }
   }
+}
+
+// Workgroups of infer_kernel: one per CU (its LDS holds all three weight
+// matrices and the intermediates, about 93 KB), at most one per tile.
+static int infer_grid(int ntiles) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  return std::min(ntiles, cus);
 }
 
 // delta[c] -= mean_c * out_scale[c] for the channels in mask (sums: channel
@@ -790,10 +872,10 @@ struct olb_closure {
       olb_status s = hip(hipMemsetAsync(sums, 0, 4 * sizeof(double), stream), "sums clear");
       if (s) return s;
     }
-    const int tiles_x = (nx + FT - 1) / FT, tiles_y = (ny + FT - 1) / FT;
-    hipLaunchKernelGGL(infer_kernel, dim3(tiles_x * tiles_y), dim3(512), 0, stream, dev_m, norm, at<bf16>(L.w1),
+    const int tiles_x = (nx + FT - 1) / FT, tiles_y = (ny + FT - 1) / FT, ntiles = tiles_x * tiles_y;
+    hipLaunchKernelGGL(infer_kernel, dim3(infer_grid(ntiles)), dim3(64 * IW), 0, stream, dev_m, norm, at<bf16>(L.w1),
                        at<bf16>(L.w2), at<bf16>(L.w3), par + 32 * 4 * 9, par + (32 * 4 * 9 + 32) + 32 * 32 * 9,
-                       par + (NPARAM - 4), nx, ny, tiles_x, dev_delta, sums);
+                       par + (NPARAM - 4), nx, ny, tiles_x, ntiles, dev_delta, sums);
     if (sums)
       hipLaunchKernelGGL(project_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, dev_delta, P, norm, sums,
                          conserve_mask);
@@ -1126,11 +1208,11 @@ olb_status olb_closure_forward_noalloc(int32_t nx, int32_t ny, const float* dev_
   hipStream_t st = (hipStream_t)hip_stream;
   const int n = 32 * kp_of(4) + 32 * kp_of(32) + 16 * kp_of(32);
   hipLaunchKernelGGL(pack_weights, dim3((n + 255) / 256), dim3(256), 0, st, dev_params, W1, W2, W3, sums);
-  const int tiles_x = (nx + FT - 1) / FT, tiles_y = (ny + FT - 1) / FT;
+  const int tiles_x = (nx + FT - 1) / FT, tiles_y = (ny + FT - 1) / FT, ntiles = tiles_x * tiles_y;
   const int P = nx * ny;
-  hipLaunchKernelGGL(infer_kernel, dim3(tiles_x * tiles_y), dim3(512), 0, st, dev_moments, nm, W1, W2, W3,
+  hipLaunchKernelGGL(infer_kernel, dim3(infer_grid(ntiles)), dim3(64 * IW), 0, st, dev_moments, nm, W1, W2, W3,
                      dev_params + 32 * 4 * 9, dev_params + (32 * 4 * 9 + 32) + 32 * 32 * 9, dev_params + (NPARAM - 4),
-                     nx, ny, tiles_x, dev_delta, sums);
+                     nx, ny, tiles_x, ntiles, dev_delta, sums);
   if (sums)
     hipLaunchKernelGGL(project_kernel, dim3((P + 255) / 256), dim3(256), 0, st, dev_delta, P, nm, sums,
                        conserve_mask);

@@ -100,10 +100,11 @@ def test_forward_matches_oracle(shape, mask):
     assert e_x < 3e-2
 
 
-@pytest.mark.parametrize("shape", [(37, 23), (64, 48), (16, 16), (5, 3), (130, 17)])
+@pytest.mark.parametrize("shape", [(37, 23), (64, 48), (16, 16), (5, 3), (130, 17), (300, 260), (512, 512)])
 def test_fused_inference_equals_layer_by_layer_forward(shape):
-    """The one-tile-per-workgroup kernel (ragged edge tiles, lattices smaller
-    than its halo) against the training path's per-layer kernels."""
+    """The fused kernel (ragged edge tiles, lattices smaller than its halo,
+    and lattices with more tiles than workgroups, where a workgroup takes
+    several tiles in turn) against the training path's per-layer kernels."""
     torch, olb = _env()
     nx, ny = shape
     params, m, _, norm = _setup(nx, ny, seed=17)

@@ -497,19 +497,22 @@ __global__ void delta_kernel(const float* __restrict__ Z3, int P, Norm nm, const
 constexpr int FT = 16;            // output tile edge
 constexpr int R0 = FT + 6, R1 = FT + 4, R2 = FT + 2;
 // weight matrices, rows padded by 8 (16-byte aligned rows)
-constexpr int WL1 = kp_of(4) + 8, WL = kp_of(32) + 8;
+constexpr int WL = kp_of(32) + 8;
 // hidden activations: 32 channels per pixel padded to 36, so that the 16
-// pixels one fragment reads start in 16 different bank pairs
+// pixels one fragment reads start in 16 different bank pairs.  Region rows
+// are stored with a stride of (output width of the layer reading them) + 16
+// pixels: an m-tile of 16 pixels that wraps to the next output row then
+// still falls on 16 different bank pairs (with the natural stride, output
+// width + 2, the pixels before and after the wrap collide two by two).
 constexpr int HS = 36;
+constexpr int S0 = R1 + 16, S1 = R2 + 16, S2 = FT + 2;  // row strides of x0, a1, a2 (a2: no wrap, FT = 16)
 // waves per inference workgroup
 constexpr int IW = 8;
 struct InferLds {
-  __attribute__((aligned(16))) bf16 w1[32 * WL1];
   __attribute__((aligned(16))) bf16 w2[32 * WL];
-  __attribute__((aligned(16))) bf16 w3[16 * WL];
-  bf16 x0[R0 * R0 * 4];
-  bf16 a1[R1 * R1 * HS];
-  bf16 a2[R2 * R2 * HS];
+  bf16 x0[R0 * S0 * 4];
+  bf16 a1[R1 * S1 * HS];
+  bf16 a2[R2 * S2 * HS];
   double part[IW][4];
 };
 static_assert(R0 * R0 <= 64 * IW, "one input pixel per thread");
@@ -524,7 +527,7 @@ __device__ __forceinline__ void stage_weights(bf16* w, const bf16* __restrict__ 
 }
 
 // MFMA layer on an R x R output region from an (R + 2) x (R + 2) input
-// region in LDS: m-tiles of 16 region pixels (row-major), wave w of the IW
+// region in LDS (rows RI pixels apart): m-tiles of 16 region pixels (row-major), wave w of the IW
 // waves taking tiles w, w + IW, ...  The product is taken transposed, weights as the A
 // operand and activations as the B operand, so that a lane receives four
 // consecutive output channels of one pixel (one 8-byte LDS store instead of
@@ -539,11 +542,59 @@ __device__ __forceinline__ void stage_weights(bf16* w, const bf16* __restrict__ 
 // MFMAs.  `wave` must be uniform (readfirstlane).  The epilogue functor gets
 // (pixel, first channel co, the four values of channels co .. co + 3), for
 // co < COUT.
-template <int CIN, int COUT, int R, int IS, typename Epi>
-__device__ __forceinline__ void lds_layer(const bf16* in, const bf16* w, const float* __restrict__ bias,
+// A lane's bias values of one layer: channels t*16 + 4g .. + 3 of each
+// n-tile t (zeros past COUT), read once per workgroup so that no global
+// read waits in the layers' epilogues.
+template <int COUT>
+struct BiasRegs {
+  static constexpr int NT = (COUT + 15) / 16;
+  f32x4 b[NT];
+  __device__ __forceinline__ void load(const float* __restrict__ bias, int lane) {
+    const int g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + 4 * g;
+      b[t] = co < COUT ? f32x4{bias[co], bias[co + 1], bias[co + 2], bias[co + 3]} : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+};
+
+// A wave's weight fragments of one layer for all K steps, held in registers:
+// lane (i, g) holds rows t*16 + i, columns ks*32 + 8g .. + 7 of the bf16
+// matrix Wt[co][k] (rows padded to 16, row length KP), read from global
+// memory once per workgroup: the values the LDS-staged rows give.
+template <int CIN, int COUT>
+struct WeightFrags {
+  static constexpr int KP = kp_of(CIN), KS = KP / 32, NT = (COUT + 15) / 16;
+  bf16x8 f[KS][NT];
+  __device__ __forceinline__ void load(const bf16* __restrict__ Wt, int lane) {
+    const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) f[ks][t] = b_frag(Wt + (size_t)(t * 16 + i) * KP + ks * 32 + 8 * g);
+  }
+};
+// Weight fragments read from an LDS copy of the matrix (row stride KP + 8).
+template <int CIN, int COUT>
+struct WeightLds {
+  static constexpr int KP = kp_of(CIN);
+  const bf16* w;
+  __device__ __forceinline__ bf16x8 frag(int ks, int t, int lane) const {
+    return b_frag(w + (t * 16 + (lane & 15)) * (KP + 8) + ks * 32 + 8 * (lane >> 4));
+  }
+};
+template <int CIN, int COUT>
+__device__ __forceinline__ bf16x8 wfrag(const WeightFrags<CIN, COUT>& w, int ks, int t, int) { return w.f[ks][t]; }
+template <int CIN, int COUT>
+__device__ __forceinline__ bf16x8 wfrag(const WeightLds<CIN, COUT>& w, int ks, int t, int lane) { return w.frag(ks, t, lane); }
+
+template <int CIN, int COUT, int R, int IS, int RI, typename Wts, typename Epi>
+__device__ __forceinline__ void lds_layer(const bf16* in, const Wts& w, const BiasRegs<COUT>& bias,
                                           int wave, int lane, Epi epi) {
   constexpr int K = 9 * CIN, KP = kp_of(CIN), KS = KP / 32, NT = (COUT + 15) / 16;
-  constexpr int NPIX = R * R, MTILES = (NPIX + 15) / 16, RI = R + 2, MW = (MTILES + IW - 1) / IW;
+  constexpr int NPIX = R * R, MTILES = (NPIX + 15) / 16, MW = (MTILES + IW - 1) / IW;
+  static_assert(RI >= R + 2, "input rows hold the output row and its two halo columns");
   static_assert(COUT % 4 == 0, "four channels per lane");
   const int i = lane & 15, g = lane >> 4;
   int base[MW];  // this lane's activation row (region pixel) of each m-tile
@@ -563,7 +614,7 @@ __device__ __forceinline__ void lds_layer(const bf16* in, const bf16* w, const f
     const int k0 = ks * 32 + 8 * g;
     bf16x8 b[NT], a[MW];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) b[t] = b_frag(w + (t * 16 + i) * (KP + 8) + k0);
+    for (int t = 0; t < NT; ++t) b[t] = wfrag(w, ks, t, lane);
 #pragma unroll
     for (int m = 0; m < MW; ++m) {
       auto at = [&](int tap, int ci) {
@@ -588,8 +639,8 @@ __device__ __forceinline__ void lds_layer(const bf16* in, const bf16* w, const f
     for (int t = 0; t < NT; ++t) {
       const int co = t * 16 + 4 * g;
       if (co >= COUT || q >= NPIX) continue;
-      epi(q, co, f32x4{acc[m][t][0] + bias[co], acc[m][t][1] + bias[co + 1], acc[m][t][2] + bias[co + 2],
-                       acc[m][t][3] + bias[co + 3]});
+      epi(q, co, f32x4{acc[m][t][0] + bias.b[t][0], acc[m][t][1] + bias.b[t][1], acc[m][t][2] + bias.b[t][2],
+                       acc[m][t][3] + bias.b[t][3]});
     }
   }
 }
@@ -625,34 +676,48 @@ __global__ void __launch_bounds__(64 * IW) infer_kernel(const double* __restrict
   };
   auto store_input = [&]() {
     if (tid >= R0 * R0) return;
+    const int r = tid / R0, c = tid - r * R0;
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch)
-      sm.x0[tid * 4 + ch] = to_bf16((float)((in[ch] - nm.in_mean[ch]) * nm.in_inv_scale[ch]));
+      sm.x0[(r * S0 + c) * 4 + ch] = to_bf16((float)((in[ch] - nm.in_mean[ch]) * nm.in_inv_scale[ch]));
   };
   int tile = blockIdx.x;
   load_input(tile);
-  stage_weights<32, kp_of(4)>(sm.w1, W1, tid);
+  // layer 2's weights in LDS; layers 1 and 3 (16 and 36 registers) in registers
   stage_weights<32, kp_of(32)>(sm.w2, W2, tid);
-  stage_weights<16, kp_of(32)>(sm.w3, W3, tid);
+  WeightFrags<4, 32> wf1;
+  WeightFrags<32, 4> wf3;
+  wf1.load(W1, lane);
+  wf3.load(W3, lane);
+  const WeightLds<32, 32> wl2{sm.w2};
   store_input();
+  BiasRegs<32> bias1, bias2;
+  BiasRegs<4> bias3;
+  bias1.load(b1, lane);
+  bias2.load(b2, lane);
+  bias3.load(b3, lane);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (; tile < ntiles; tile += gridDim.x) {
     const int ty0 = (tile / tiles_x) * FT, tx0 = (tile % tiles_x) * FT;
     // the input region (and, on the first tile, the weights) are in LDS; a1
     // was last read by the previous tile's layer 2, before its second barrier
     __syncthreads();
-    lds_layer<4, 32, R1, 4>(sm.x0, sm.w1, b1, wave, lane,
-                            [&](int q, int co, f32x4 z) { store_relu4(sm.a1 + q * HS + co, z); });
+    lds_layer<4, 32, R1, 4, S0>(sm.x0, wf1, bias1, wave, lane, [&](int q, int co, f32x4 z) {
+      const int r = q / R1, c = q - r * R1;
+      store_relu4(sm.a1 + (r * S1 + c) * HS + co, z);
+    });
     // a1 complete; the input region is free (layer 2 writes a2, which the
     // previous tile's layer 3 read before this tile's first barrier)
     __syncthreads();
     const int next = tile + gridDim.x;
     if (next < ntiles) load_input(next);
-    lds_layer<32, 32, R2, HS>(sm.a1, sm.w2, b2, wave, lane,
-                              [&](int q, int co, f32x4 z) { store_relu4(sm.a2 + q * HS + co, z); });
+    lds_layer<32, 32, R2, HS, S1>(sm.a1, wl2, bias2, wave, lane, [&](int q, int co, f32x4 z) {
+      const int r = q / R2, c = q - r * R2;
+      store_relu4(sm.a2 + (r * S2 + c) * HS + co, z);
+    });
     if (next < ntiles) store_input();
     __syncthreads();
-    lds_layer<32, 4, FT, HS>(sm.a2, sm.w3, b3, wave, lane, [&](int q, int, f32x4 z) {
+    lds_layer<32, 4, FT, HS, S2>(sm.a2, wf3, bias3, wave, lane, [&](int q, int, f32x4 z) {
       const int r = q / FT, c = q - r * FT;
       const int gy = ty0 + r, gx = tx0 + c;
       if (gy < ny && gx < nx) {

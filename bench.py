@@ -616,8 +616,8 @@ def run_closure(args):
                                               "plain_rms": [b for _, b in roll_p],
                                               "closure_rms": [b for _, b in roll_f]},
                        "order": "[plain coarse, coarse + closure]", "skipped_nodes": skipped}},
-        "roofline": {"bound": "mfma", "kernel": "network forward (fused: one 16x16 tile per workgroup, "
-                               "three bf16 implicit-GEMM convolutions in LDS, plus the projection)",
+        "roofline": {"bound": "mfma", "kernel": "network forward (fused: persistent workgroups over 16x16 "
+                               "tiles, three bf16 implicit-GEMM convolutions in LDS, plus the projection)",
                      "achieved": round(fwd_tflops, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(fwd_tflops / MFMA_BF16_PEAK_TFLOPS, 5), "traffic": None,
                      "forward_ms": round(fwd_s * 1e3, 4)},

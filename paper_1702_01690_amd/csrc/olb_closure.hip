@@ -369,6 +369,13 @@ struct Norm {
   float in_mean[4], in_inv_scale[4], out_scale[4];
 };
 
+// n 32-bit words of p set to zero: the clears on the forward and training
+// paths, as a kernel rather than a memset node, so that callers may capture
+// those paths in a HIP graph
+__global__ void zero_words(unsigned* __restrict__ p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
 // moment planes (FP64) -> normalised bf16 input [p][4]
 __global__ void prep_kernel(const double* __restrict__ m, int P, Norm nm, bf16* __restrict__ x) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -933,10 +940,7 @@ struct olb_closure {
     using namespace olbk;
     const float* par = at<float>(L.par);
     double* sums = conserve_mask ? at<double>(L.sums) : nullptr;
-    if (sums) {
-      olb_status s = hip(hipMemsetAsync(sums, 0, 4 * sizeof(double), stream), "sums clear");
-      if (s) return s;
-    }
+    if (sums) hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned*>(sums), 8);
     const int tiles_x = (nx + FT - 1) / FT, tiles_y = (ny + FT - 1) / FT, ntiles = tiles_x * tiles_y;
     hipLaunchKernelGGL(infer_kernel, dim3(infer_grid(ntiles)), dim3(64 * IW), 0, stream, dev_m, norm, at<bf16>(L.w1),
                        at<bf16>(L.w2), at<bf16>(L.w3), par + 32 * 4 * 9, par + (32 * 4 * 9 + 32) + 32 * 32 * 9,
@@ -954,8 +958,7 @@ struct olb_closure {
     if (s) return s;
     double* sums = at<double>(L.sums);
     if (conserve_mask) {
-      s = hip(hipMemsetAsync(sums, 0, 4 * sizeof(double), stream), "sums clear");
-      if (s) return s;
+      hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned*>(sums), 8);
       const int blocks = std::min(1024, (P + 255) / 256);
       hipLaunchKernelGGL(output_sums, dim3(blocks), dim3(256), 0, stream, at<float>(L.z3), P, sums);
     }
@@ -967,9 +970,10 @@ struct olb_closure {
   olb_status backward(const double* dev_m, const double* dev_ref) {
     using namespace olbk;
     float* grad = at<float>(L.grad);
-    olb_status s = hip(hipMemsetAsync(grad, 0, NPARAM * 4, stream), "grad clear");
-    if (s) return s;
-    s = hip(hipMemsetAsync(at<float>(L.loss), 0, 4, stream), "loss clear");
+    hipLaunchKernelGGL(zero_words, dim3((NPARAM + 255) / 256), dim3(256), 0, stream, reinterpret_cast<unsigned*>(grad),
+                       NPARAM);
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned*>(at<float>(L.loss)), 1);
+    olb_status s = hip(hipGetLastError(), "clear kernels");
     if (s) return s;
     hipLaunchKernelGGL(loss_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, at<float>(L.z3), dev_m, dev_ref,
                        P, norm, at<bf16>(L.g3), at<float>(L.loss));
@@ -1177,8 +1181,8 @@ olb_status correct(olb_closure* c, olb_ctx* coarse, const double* target, double
     if (s) return s;
     target = c->at<double>(c->L.delta);
   }
-  s = c->hip(hipMemsetAsync(c->at<int>(c->L.skip), 0, 4, c->stream), "skip clear");
-  if (s) return s;
+  hipLaunchKernelGGL(olbk::zero_words, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<unsigned*>(c->at<int>(c->L.skip)),
+                     1);
   dim3 grid((c->nx + 63) / 64, c->ny);
   if (v.real_bytes == 8)
     hipLaunchKernelGGL(olbk::apply_kernel<double>, grid, dim3(64), 0, c->stream, m_buf, target, absolute, v.g,

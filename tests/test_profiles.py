@@ -15,7 +15,7 @@ def _entries():
         return json.load(fh)
 
 
-@pytest.mark.parametrize("workload", ["wave2048", "spinodal4096"])
+@pytest.mark.parametrize("workload", ["wave2048", "spinodal4096", "channels"])
 def test_traffic_entry_is_consistent(workload):
     e = _entries()[workload]
     assert len(e["kernel_hash"]) == 16

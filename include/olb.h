@@ -232,7 +232,10 @@ void olb_batch_free(olb_batch* b);
  * outputs scaled by out_scale.  Convolutions run on the bf16 matrix cores
  * with FP32 accumulation; activations and back-propagated gradients are
  * rounded to bf16 (nearest even) between layers; parameters, gradients and
- * Adam moments are FP32.
+ * Adam moments are FP32.  Sums over nodes (gradients, loss, the projection's
+ * channel sums) add per-workgroup partial sums in a fixed order, without
+ * atomics: on one device and for one lattice size, every call with the same
+ * inputs gives the same bits.
  *
  * Parameters: one FP32 vector of OLB_CLOSURE_NPARAM values
  *   [W1 (32x4x3x3) | b1 (32) | W2 (32x32x3x3) | b2 (32) | W3 (4x32x3x3) | b3 (4)]
@@ -263,7 +266,9 @@ olb_status olb_closure_get_params(olb_closure* c, float* params);
 olb_status olb_closure_forward(olb_closure* c, const double* dev_moments, double* dev_delta);
 /* The same through the training path's kernels (one launch per layer, the
  * activations in the workspace) instead of the fused one-tile-per-workgroup
- * kernel; without projection (mask 0) the two agree to the bit. */
+ * kernel; without projection (mask 0) the two agree to the bit, with it to
+ * FP64 rounding of the channel sums (which the two add in different
+ * orders). */
 olb_status olb_closure_forward_layers(olb_closure* c, const double* dev_moments, double* dev_delta);
 /* Conservative projection of forward / apply: bit c of mask (c = 0 n,
  * 1 u_x, 2 u_y, 3 T) removes the lattice mean of that correction channel, so
@@ -305,13 +310,13 @@ void olb_closure_free(olb_closure* c);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops that forbid hipMalloc): olb_closure_forward without
- * a closure object or workspace.  Same kernels and result (network output of
+ * a closure object or workspace.  Same kernels and bits (network output of
  * dev_moments, device double [4][ny][nx], scaled by out_scale and projected
  * by conserve_mask, into dev_delta, device double [4][ny][nx]); the
  * parameters come from dev_params, device FP32 [OLB_CLOSURE_NPARAM] in the
  * layout above, and the normalisation from the host arrays (as
  * olb_closure_set_norm).  The bf16 weight matrices and the projection's
- * channel sums live in a static device array of 32 KiB that the library
+ * partial channel sums live in a static device array of 40 KiB that the library
  * holds on every GPU it runs on until the process ends; the call allocates
  * nothing and enqueues three kernels on hip_stream (no memset).  Every call
  * on a GPU overwrites that array: calls that overlap on one GPU (other

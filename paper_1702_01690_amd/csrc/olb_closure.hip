@@ -5,10 +5,15 @@
 // a coarse lattice to a correction of those moments.  Every convolution is an
 // implicit GEMM on the bf16 matrix cores with FP32 accumulation: forward
 // (v_mfma_f32_16x16x32_bf16, K steps of 32), backward-data (fused with the
-// ReLU mask) and backward-weight (pixel reduction, FP32 atomics) on
+// ReLU mask) and backward-weight (pixel reduction) on
 // v_mfma_f32_16x16x16_bf16.  Master weights, Adam
 // moments and gradients are FP32; activations and gradients entering the
 // matrix cores are rounded to bf16 (round to nearest even).
+//
+// Every sum over pixels (weight and bias gradients, the loss, the channel
+// sums of the conservative projection) is formed from per-workgroup partial
+// sums added in a fixed order, never with atomics: for a given lattice size
+// and device, a computation gives the same bits on every run.
 //
 // Layouts: activations [pixel][channel], pixel = y * nx + x; parameters are
 // one FP32 vector [W1 | b1 | W2 | b2 | W3 | b3] with W[co][ci][ky][kx];
@@ -251,13 +256,14 @@ __global__ void __launch_bounds__(256) conv_bwd_data(const bf16* __restrict__ G,
 }
 
 // --------------------------------------------------------- backward weight --
-// dW[co][ci][tap] += sum_p G[p][co] X[p + off(tap)][ci]  (GEMM M = COUT,
+// dW[co][ci][tap] = sum_p G[p][co] X[p + off(tap)][ci]  (GEMM M = COUT,
 // N = 9 CIN, reduction over pixels).  Each wave owns one 16 x 16 output tile
 // (blockIdx.x picks 4 tiles) and reduces it over one pixel chunk
-// (blockIdx.y); FP32 atomics add the chunks' partial sums.
+// (blockIdx.y), whose partial sums it writes to row blockIdx.y of
+// dWp[chunk][COUT * CIN * 9]; sum_segments adds the rows in order.
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) conv_bwd_weight(const bf16* __restrict__ G, const bf16* __restrict__ X,
-                                                       float* __restrict__ dW, int nx, int ny, int chunk) {
+                                                       float* __restrict__ dWp, int nx, int ny, int chunk) {
   constexpr int K = 9 * CIN, KP = (K + 15) / 16 * 16, MT = (COUT + 15) / 16, NTK = KP / 16;
   constexpr int TILES = MT * NTK;
   const int P = nx * ny;
@@ -306,17 +312,19 @@ __global__ void __launch_bounds__(256) conv_bwd_weight(const bf16* __restrict__ 
   const f32x4 acc = acc0 + acc1;
   // lane holds D[4g + v][i]: output channel mt*16 + 4g + v, k = nt*16 + i
   if (!k_ok) return;
+  float* row = dWp + (size_t)blockIdx.y * (COUT * CIN * 9);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int c = mt * 16 + 4 * g + v;
-    if (c < COUT) atomicAdd(&dW[((size_t)c * CIN + ci) * 9 + tap], acc[v]);
+    if (c < COUT) row[(c * CIN + ci) * 9 + tap] = acc[v];
   }
 }
 
-// db[c] += sum_p G[p][c]: thread (row r, channel c) of a block sums channel c
-// over rows r, r + R, ... (coalesced rows of C values), then one LDS reduction
+// Partial bias gradients dbp[block][c] = sum over the block's pixels of
+// G[p][c]: thread (row r, channel c) sums channel c over rows r, r + R, ...
+// (coalesced rows of C values), then one LDS reduction
 template <int C>
-__global__ void __launch_bounds__(256) bias_grad(const bf16* __restrict__ G, float* __restrict__ db, int P) {
+__global__ void __launch_bounds__(256) bias_grad(const bf16* __restrict__ G, float* __restrict__ dbp, int P) {
   constexpr int R = 256 / C;
   __shared__ float part[256];
   const int c = threadIdx.x % C, r = threadIdx.x / C;
@@ -328,7 +336,74 @@ __global__ void __launch_bounds__(256) bias_grad(const bf16* __restrict__ G, flo
     float t = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) t += part[j * C + threadIdx.x];
-    atomicAdd(&db[threadIdx.x], t);
+    dbp[(size_t)blockIdx.x * C + threadIdx.x] = t;
+  }
+}
+
+// Fixed-order sums of row-major partial sums: dst[j] = sum over rows r of
+// src[r * n + j], for up to 8 segments (blockIdx.y).  A block takes C columns
+// (the smallest power of two >= n, at most 256) and R = 256 / C row phases:
+// thread (r, c) adds rows r, r + R, ... in order, then a tree over the phases.
+// The order depends only on (rows, n), so every run gives the same bits.  The
+// rows are loaded 16 at a time before they are added, so that a thread waits
+// for one load latency per 16 rows rather than per row.
+struct SumSeg {
+  const float* src;
+  float* dst;
+  int rows, n;
+};
+struct SumSegs {
+  SumSeg s[8];
+};
+__global__ void __launch_bounds__(256) sum_segments(SumSegs segs) {
+  const SumSeg sg = segs.s[blockIdx.y];
+  int C = 256;
+  while (C > 1 && C / 2 >= sg.n) C >>= 1;
+  if ((int)blockIdx.x * C >= sg.n) return;  // the whole block: no column here
+  const int R = 256 / C, c = threadIdx.x % C, r = threadIdx.x / C;
+  const int col = blockIdx.x * C + c;
+  __shared__ float red[256];
+  constexpr int U = 16;
+  float acc = 0.f;
+  if (col < sg.n) {
+    const float* src = sg.src + col;
+    int row = r;
+    for (; row + (U - 1) * R < sg.rows; row += U * R) {
+      float v[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) v[j] = src[(size_t)(row + j * R) * sg.n];
+#pragma unroll
+      for (int j = 0; j < U; ++j) acc += v[j];
+    }
+    for (; row < sg.rows; row += R) acc += src[(size_t)row * sg.n];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = R / 2; h > 0; h >>= 1) {
+    if (r < h) red[r * C + c] += red[(r + h) * C + c];
+    __syncthreads();
+  }
+  if (r == 0 && col < sg.n) sg.dst[col] = red[c];
+}
+
+// Most partial sums of the projection (workgroups of output_sums and of
+// infer_kernel)
+constexpr int MAX_PARTS = 256;
+
+// Fixed-order total of nparts <= MAX_PARTS rows of four FP64 partial sums,
+// for a block of 256 threads: thread t loads row t, then a tree over the
+// threads.  Every block (and every run) gets the same bits; red[c][0] holds
+// channel c's total on return.  All threads of the block must call it.
+__device__ __forceinline__ void block_total4(const double* __restrict__ part, int nparts, double (*red)[256]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) red[c][t] = t < nparts ? part[(size_t)t * 4 + c] : 0.0;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[c][t] += red[c][t + h];
+    __syncthreads();
   }
 }
 
@@ -369,9 +444,9 @@ struct Norm {
   float in_mean[4], in_inv_scale[4], out_scale[4];
 };
 
-// n 32-bit words of p set to zero: the clears on the forward and training
-// paths, as a kernel rather than a memset node, so that callers may capture
-// those paths in a HIP graph
+// n 32-bit words of p set to zero (the correction's skip counter), as a
+// kernel rather than a memset node, so that callers may capture the
+// correction in a HIP graph
 __global__ void zero_words(unsigned* __restrict__ p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
@@ -386,15 +461,15 @@ __global__ void prep_kernel(const double* __restrict__ m, int P, Norm nm, bf16* 
 }
 
 // MSE loss on the normalised correction, whose target is (reference - m) /
-// out_scale; G3 = dL/dZ3 (bf16), loss accumulated
-__global__ void loss_kernel(const float* __restrict__ Z3, const double* __restrict__ m,
-                            const double* __restrict__ ref, int P, Norm nm, bf16* __restrict__ G3,
-                            float* __restrict__ loss) {
+// out_scale; G3 = dL/dZ3 (bf16); lossp[block] = the block's share of the loss
+// (pixels blockIdx.x * 256 + threadIdx.x, stepping by the grid)
+__global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ Z3, const double* __restrict__ m,
+                                                   const double* __restrict__ ref, int P, Norm nm,
+                                                   bf16* __restrict__ G3, float* __restrict__ lossp) {
   __shared__ float part[256];
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const float scale = 2.0f / (4.0f * (float)P);
   float l = 0.f;
-  if (p < P) {
-    const float scale = 2.0f / (4.0f * (float)P);
+  for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const size_t o = (size_t)c * P + p;
@@ -410,17 +485,14 @@ __global__ void loss_kernel(const float* __restrict__ Z3, const double* __restri
     if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(loss, part[0] / (4.0f * (float)P));
+  if (threadIdx.x == 0) lossp[blockIdx.x] = part[0] / (4.0f * (float)P);
 }
 
-// FP32 master parameters -> bf16 weight matrices (padded) of the three layers;
-// clear4, when not null, gets four zeros (the projection's channel sums, so
-// that no memset has to be enqueued)
+// FP32 master parameters -> bf16 weight matrices (padded) of the three layers
 __global__ void pack_weights(const float* __restrict__ w, bf16* __restrict__ W1, bf16* __restrict__ W2,
-                             bf16* __restrict__ W3, double* __restrict__ clear4) {
+                             bf16* __restrict__ W3) {
   // layer l: Cin, Cout, offset of W in the flat vector
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (clear4 && idx < 4) clear4[idx] = 0.0;
   constexpr int KP1 = kp_of(4), KP2 = kp_of(32), KP3 = kp_of(32);
   constexpr int N1 = 32 * KP1, N2 = 32 * KP2, N3 = 16 * KP3;
   constexpr int O1 = 0, O2 = 32 * 4 * 9 + 32, O3 = O2 + 32 * 32 * 9 + 32;
@@ -455,8 +527,10 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
   w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
-// channel sums of the network output (double), for the conservative projection
-__global__ void __launch_bounds__(256) output_sums(const float* __restrict__ Z3, int P, double* __restrict__ sums) {
+// partial channel sums of the network output (double), for the conservative
+// projection: part[block][c] over pixels blockIdx.x * 256 + threadIdx.x,
+// stepping by the grid (at most MAX_PARTS blocks)
+__global__ void __launch_bounds__(256) output_sums(const float* __restrict__ Z3, int P, double* __restrict__ part4) {
   __shared__ double part[4][256];
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256)
@@ -471,18 +545,22 @@ __global__ void __launch_bounds__(256) output_sums(const float* __restrict__ Z3,
       for (int c = 0; c < 4; ++c) part[c][threadIdx.x] += part[c][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x < 4) atomicAdd(&sums[threadIdx.x], part[threadIdx.x][0]);
+  if (threadIdx.x < 4) part4[blockIdx.x * 4 + threadIdx.x] = part[threadIdx.x][0];
 }
 
 // network output (normalised) -> correction planes (FP64); channels in
-// conserve_mask lose their lattice mean (sums from output_sums)
-__global__ void delta_kernel(const float* __restrict__ Z3, int P, Norm nm, const double* __restrict__ sums,
-                             int conserve_mask, double* __restrict__ delta) {
+// conserve_mask lose their lattice mean (the nparts partial sums of
+// output_sums, totalled in a fixed order); 256 threads per block
+__global__ void __launch_bounds__(256) delta_kernel(const float* __restrict__ Z3, int P, Norm nm,
+                                                    const double* __restrict__ part4, int nparts,
+                                                    int conserve_mask, double* __restrict__ delta) {
+  __shared__ double red[4][256];
+  if (conserve_mask) block_total4(part4, nparts, red);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const double mean = ((conserve_mask >> c) & 1) ? sums[c] / (double)P : 0.0;
+    const double mean = ((conserve_mask >> c) & 1) ? red[c][0] / (double)P : 0.0;
     delta[(size_t)c * P + p] = ((double)Z3[(size_t)p * 4 + c] - mean) * (double)nm.out_scale[c];
   }
 }
@@ -663,7 +741,7 @@ __global__ void __launch_bounds__(64 * IW) infer_kernel(const double* __restrict
                                                     const bf16* __restrict__ W3, const float* __restrict__ b1,
                                                     const float* __restrict__ b2, const float* __restrict__ b3,
                                                     int nx, int ny, int tiles_x, int ntiles,
-                                                    double* __restrict__ delta, double* __restrict__ sums) {
+                                                    double* __restrict__ delta, double* __restrict__ part4) {
   __shared__ InferLds sm;
   const int P = nx * ny;
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -736,9 +814,10 @@ __global__ void __launch_bounds__(64 * IW) infer_kernel(const double* __restrict
       }
     });
   }
-  if (sums) {
+  if (part4) {
     // lanes 0..15 hold all four channels of their pixels (the others hold
-    // zeros): fold the 64 lanes, then the waves
+    // zeros): fold the 64 lanes, then the waves, into this workgroup's row
+    // of partial sums
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       double v = s[k];
@@ -752,30 +831,35 @@ __global__ void __launch_bounds__(64 * IW) infer_kernel(const double* __restrict
       double t = 0.0;
 #pragma unroll
       for (int w = 0; w < IW; ++w) t += sm.part[w][tid];
-      atomicAdd(&sums[tid], t);
+      part4[blockIdx.x * 4 + tid] = t;
     }
   }
 }
 
 // Workgroups of infer_kernel: one per CU (its LDS holds all three weight
-// matrices and the intermediates, about 93 KB), at most one per tile.
+// matrices and the intermediates, about 93 KB), at most one per tile and at
+// most MAX_PARTS (one row of projection partial sums each).
 static int infer_grid(int ntiles) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus < 1)
     cus = 256;
-  return std::min(ntiles, cus);
+  return std::min(std::min(ntiles, cus), MAX_PARTS);
 }
 
-// delta[c] -= mean_c * out_scale[c] for the channels in mask (sums: channel
-// totals of the normalised output over P nodes)
-__global__ void project_kernel(double* __restrict__ delta, int P, Norm nm, const double* __restrict__ sums,
-                               int mask) {
+// delta[c] -= mean_c * out_scale[c] for the channels in mask; the channel
+// totals of the normalised output over P nodes are the nparts rows of
+// partial sums of infer_kernel, totalled in a fixed order; 256 threads per
+// block
+__global__ void __launch_bounds__(256) project_kernel(double* __restrict__ delta, int P, Norm nm,
+                                                      const double* __restrict__ part4, int nparts, int mask) {
+  __shared__ double red[4][256];
+  block_total4(part4, nparts, red);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
 #pragma unroll
   for (int c = 0; c < 4; ++c)
-    if ((mask >> c) & 1) delta[(size_t)c * P + p] -= sums[c] / (double)P * (double)nm.out_scale[c];
+    if ((mask >> c) & 1) delta[(size_t)c * P + p] -= red[c][0] / (double)P * (double)nm.out_scale[c];
 }
 
 // f <- f + f^eq(m') - f^eq(m) with m' = m + dm (absolute == 0) or m' = dm
@@ -819,20 +903,20 @@ __global__ void apply_kernel(const double* __restrict__ m, const double* __restr
 // --------------------------------------------------------------------------
 // device scratch of the allocation-free inference entry point
 // --------------------------------------------------------------------------
-// The bf16 weight matrices of the three layers and the projection's four
-// channel sums.  One copy per GPU, held until the process ends; every call
-// on a GPU overwrites it.  In host code the name stands for a host-side
+// The bf16 weight matrices of the three layers and the projection's partial
+// channel sums (one row of four per inference workgroup).  One copy per GPU,
+// held until the process ends; every call on a GPU overwrites it.  In host code the name stands for a host-side
 // stand-in: kernels and copies get its device address from
 // hipGetSymbolAddress (noalloc_scratch below), never the name itself.
 namespace {
 constexpr size_t NA_W1 = 0;
 constexpr size_t NA_W2 = NA_W1 + 32 * olbk::kp_of(4) * sizeof(olbk::bf16);
 constexpr size_t NA_W3 = NA_W2 + 32 * olbk::kp_of(32) * sizeof(olbk::bf16);
-constexpr size_t NA_SUMS = NA_W3 + 16 * olbk::kp_of(32) * sizeof(olbk::bf16);
-constexpr size_t NA_USED = NA_SUMS + 4 * sizeof(double);
-constexpr size_t NA_BYTES = 32768;
+constexpr size_t NA_PART = NA_W3 + 16 * olbk::kp_of(32) * sizeof(olbk::bf16);
+constexpr size_t NA_USED = NA_PART + olbk::MAX_PARTS * 4 * sizeof(double);
+constexpr size_t NA_BYTES = 40960;
 static_assert(NA_USED <= NA_BYTES, "scratch layout");
-static_assert(NA_SUMS % 8 == 0, "sums alignment");
+static_assert(NA_PART % 8 == 0, "partial sums alignment");
 }  // namespace
 static __device__ __align__(256) unsigned char scratch[NA_BYTES];
 
@@ -847,8 +931,46 @@ static_assert(NPARAM == OLB_CLOSURE_NPARAM, "parameter count");
 constexpr size_t AL = 256;
 size_t al(size_t v) { return (v + AL - 1) / AL * AL; }
 
+// Pixel chunks of the weight-gradient kernel: about 512 workgroups (tile
+// groups x chunks), chunks of a multiple of 16 pixels
+template <int CIN, int COUT>
+struct BwdWeightGrid {
+  static constexpr int tiles = ((COUT + 15) / 16) * (olbk::kp_of(CIN) / 16);
+  static constexpr int groups = (tiles + 3) / 4;
+  int chunk, nchunks;
+  explicit BwdWeightGrid(int P) {
+    const int chunks = std::max(1, std::min((P + 63) / 64, 512 / groups));
+    chunk = ((P + chunks - 1) / chunks + 15) / 16 * 16;
+    nchunks = (P + chunk - 1) / chunk;
+  }
+};
+int bias_blocks(int P) { return std::min(1024, std::max(1, P / 256)); }
+int loss_blocks(int P) { return std::min(1024, (P + 255) / 256); }
+
+// Rows of partial sums of the backward pass, in the order of the parameter
+// vector's blocks: W1, b1, W2, b2, W3, b3, then the loss
+struct GradParts {
+  int rows[7], n[7];
+  size_t off[7], floats;
+  explicit GradParts(int P) {
+    rows[0] = BwdWeightGrid<4, 32>(P).nchunks;
+    rows[2] = BwdWeightGrid<32, 32>(P).nchunks;
+    rows[4] = BwdWeightGrid<32, 4>(P).nchunks;
+    rows[1] = rows[3] = rows[5] = bias_blocks(P);
+    rows[6] = loss_blocks(P);
+    const int ns[7] = {32 * 4 * 9, 32, 32 * 32 * 9, 32, 4 * 32 * 9, 4, 1};
+    floats = 0;
+    for (int k = 0; k < 7; ++k) {
+      n[k] = ns[k];
+      off[k] = floats;
+      floats += (size_t)rows[k] * n[k];
+    }
+  }
+};
+
 struct CLayout {
-  size_t x0, z1, a1, z2, a2, z3, g3, g2, g1, mom, delta, par, grad, am, av, w1, w2, w3, loss, skip, sums, total;
+  size_t x0, z1, a1, z2, a2, z3, g3, g2, g1, mom, delta, par, grad, am, av, w1, w2, w3, loss, skip, part4, gpart,
+      total;
 };
 
 CLayout clayout(int nx, int ny) {
@@ -876,7 +998,8 @@ CLayout clayout(int nx, int ny) {
   L.w3 = take(16 * olbk::kp_of(32) * 2);
   L.loss = take(4);
   L.skip = take(4);
-  L.sums = take(4 * 8);
+  L.part4 = take(olbk::MAX_PARTS * 4 * 8);
+  L.gpart = take(GradParts((int)P).floats * 4);
   L.total = o;
   return L;
 }
@@ -939,15 +1062,15 @@ struct olb_closure {
   olb_status infer(const double* dev_m, double* dev_delta) {
     using namespace olbk;
     const float* par = at<float>(L.par);
-    double* sums = conserve_mask ? at<double>(L.sums) : nullptr;
-    if (sums) hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned*>(sums), 8);
+    double* part4 = conserve_mask ? at<double>(L.part4) : nullptr;
     const int tiles_x = (nx + FT - 1) / FT, tiles_y = (ny + FT - 1) / FT, ntiles = tiles_x * tiles_y;
-    hipLaunchKernelGGL(infer_kernel, dim3(infer_grid(ntiles)), dim3(64 * IW), 0, stream, dev_m, norm, at<bf16>(L.w1),
+    const int grid = infer_grid(ntiles);
+    hipLaunchKernelGGL(infer_kernel, dim3(grid), dim3(64 * IW), 0, stream, dev_m, norm, at<bf16>(L.w1),
                        at<bf16>(L.w2), at<bf16>(L.w3), par + 32 * 4 * 9, par + (32 * 4 * 9 + 32) + 32 * 32 * 9,
-                       par + (NPARAM - 4), nx, ny, tiles_x, ntiles, dev_delta, sums);
-    if (sums)
-      hipLaunchKernelGGL(project_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, dev_delta, P, norm, sums,
-                         conserve_mask);
+                       par + (NPARAM - 4), nx, ny, tiles_x, ntiles, dev_delta, part4);
+    if (part4)
+      hipLaunchKernelGGL(project_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, dev_delta, P, norm, part4,
+                         grid, conserve_mask);
     return hip(hipGetLastError(), "closure inference");
   }
 
@@ -956,65 +1079,66 @@ struct olb_closure {
     using namespace olbk;
     olb_status s = forward(dev_m, false);
     if (s) return s;
-    double* sums = at<double>(L.sums);
-    if (conserve_mask) {
-      hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned*>(sums), 8);
-      const int blocks = std::min(1024, (P + 255) / 256);
-      hipLaunchKernelGGL(output_sums, dim3(blocks), dim3(256), 0, stream, at<float>(L.z3), P, sums);
-    }
-    hipLaunchKernelGGL(delta_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, at<float>(L.z3), P, norm, sums,
-                       conserve_mask, dev_delta);
+    double* part4 = at<double>(L.part4);
+    const int nparts = std::min(MAX_PARTS, (P + 255) / 256);
+    if (conserve_mask)
+      hipLaunchKernelGGL(output_sums, dim3(nparts), dim3(256), 0, stream, at<float>(L.z3), P, part4);
+    hipLaunchKernelGGL(delta_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, at<float>(L.z3), P, norm, part4,
+                       nparts, conserve_mask, dev_delta);
     return hip(hipGetLastError(), "delta kernel");
   }
 
+  // Gradient of the loss for every parameter, and the loss: each kernel
+  // writes partial sums (per pixel chunk or block) to its rows of L.gpart,
+  // which sum_segments then adds in a fixed order into L.grad and L.loss.
   olb_status backward(const double* dev_m, const double* dev_ref) {
     using namespace olbk;
-    float* grad = at<float>(L.grad);
-    hipLaunchKernelGGL(zero_words, dim3((NPARAM + 255) / 256), dim3(256), 0, stream, reinterpret_cast<unsigned*>(grad),
-                       NPARAM);
-    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned*>(at<float>(L.loss)), 1);
-    olb_status s = hip(hipGetLastError(), "clear kernels");
-    if (s) return s;
-    hipLaunchKernelGGL(loss_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, at<float>(L.z3), dev_m, dev_ref,
-                       P, norm, at<bf16>(L.g3), at<float>(L.loss));
-    const int O2 = 32 * 4 * 9 + 32, O3 = O2 + 32 * 32 * 9 + 32;
-    const int bias_blocks = std::min(1024, std::max(1, P / 256));
+    const GradParts gp(P);
+    float* part = at<float>(L.gpart);
+    hipLaunchKernelGGL(loss_kernel, dim3(gp.rows[6]), dim3(256), 0, stream, at<float>(L.z3), dev_m, dev_ref, P,
+                       norm, at<bf16>(L.g3), part + gp.off[6]);
     // layer 3
-    launch_bwd_weight<32, 4>(at<bf16>(L.g3), at<bf16>(L.a2), grad + O3);
-    hipLaunchKernelGGL((bias_grad<4>), dim3(bias_blocks), dim3(256), 0, stream, at<bf16>(L.g3),
-                       grad + O3 + 4 * 32 * 9, P);
+    launch_bwd_weight<32, 4>(at<bf16>(L.g3), at<bf16>(L.a2), part + gp.off[4]);
+    hipLaunchKernelGGL((bias_grad<4>), dim3(gp.rows[5]), dim3(256), 0, stream, at<bf16>(L.g3), part + gp.off[5], P);
     hipLaunchKernelGGL((conv_bwd_data<32, 4>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.g3),
                        at<bf16>(L.w3), at<float>(L.z2), at<bf16>(L.g2), nx, ny);
     // layer 2
-    launch_bwd_weight<32, 32>(at<bf16>(L.g2), at<bf16>(L.a1), grad + O2);
-    hipLaunchKernelGGL((bias_grad<32>), dim3(bias_blocks), dim3(256), 0, stream, at<bf16>(L.g2),
-                       grad + O2 + 32 * 32 * 9, P);
+    launch_bwd_weight<32, 32>(at<bf16>(L.g2), at<bf16>(L.a1), part + gp.off[2]);
+    hipLaunchKernelGGL((bias_grad<32>), dim3(gp.rows[3]), dim3(256), 0, stream, at<bf16>(L.g2), part + gp.off[3],
+                       P);
     hipLaunchKernelGGL((conv_bwd_data<32, 32>), dim3(pix_blocks()), dim3(256), 0, stream, at<bf16>(L.g2),
                        at<bf16>(L.w2), at<float>(L.z1), at<bf16>(L.g1), nx, ny);
     // layer 1 (the input needs no gradient)
-    launch_bwd_weight<4, 32>(at<bf16>(L.g1), at<bf16>(L.x0), grad);
-    hipLaunchKernelGGL((bias_grad<32>), dim3(bias_blocks), dim3(256), 0, stream, at<bf16>(L.g1),
-                       grad + 32 * 4 * 9, P);
+    launch_bwd_weight<4, 32>(at<bf16>(L.g1), at<bf16>(L.x0), part + gp.off[0]);
+    hipLaunchKernelGGL((bias_grad<32>), dim3(gp.rows[1]), dim3(256), 0, stream, at<bf16>(L.g1), part + gp.off[1],
+                       P);
+    // the parameter vector's blocks follow each other in gp's order
+    SumSegs segs{};
+    float* dst = at<float>(L.grad);
+    int bx = 1;
+    for (int k = 0; k < 7; ++k) {
+      segs.s[k] = SumSeg{part + gp.off[k], k < 6 ? dst : at<float>(L.loss), gp.rows[k], gp.n[k]};
+      if (k < 6) dst += gp.n[k];
+      bx = std::max(bx, (gp.n[k] + 255) / 256);
+    }
+    hipLaunchKernelGGL(sum_segments, dim3(bx, 7), dim3(256), 0, stream, segs);
     return hip(hipGetLastError(), "closure backward");
   }
 
-  // about 512 workgroups per weight gradient: tile groups x pixel chunks
+  // about 512 workgroups per weight gradient: tile groups x pixel chunks;
+  // dWp receives one row of partial sums per chunk
   template <int CIN, int COUT>
-  void launch_bwd_weight(const olbk::bf16* G, const olbk::bf16* X, float* dW) {
-    constexpr int tiles = ((COUT + 15) / 16) * (olbk::kp_of(CIN) / 16);
-    constexpr int groups = (tiles + 3) / 4;
-    const int chunks = std::max(1, std::min((P + 63) / 64, 512 / groups));
-    const int chunk = ((P + chunks - 1) / chunks + 15) / 16 * 16;
-    const int nchunks = (P + chunk - 1) / chunk;
-    hipLaunchKernelGGL((olbk::conv_bwd_weight<CIN, COUT>), dim3(groups, nchunks), dim3(256), 0, stream, G, X, dW,
-                       nx, ny, chunk);
+  void launch_bwd_weight(const olbk::bf16* G, const olbk::bf16* X, float* dWp) {
+    const BwdWeightGrid<CIN, COUT> g(P);
+    hipLaunchKernelGGL((olbk::conv_bwd_weight<CIN, COUT>), dim3(BwdWeightGrid<CIN, COUT>::groups, g.nchunks),
+                       dim3(256), 0, stream, G, X, dWp, nx, ny, g.chunk);
   }
 
   olb_status pack() {
     using namespace olbk;
     const int n = 32 * kp_of(4) + 32 * kp_of(32) + 16 * kp_of(32);
     hipLaunchKernelGGL(pack_weights, dim3((n + 255) / 256), dim3(256), 0, stream, at<float>(L.par),
-                       at<bf16>(L.w1), at<bf16>(L.w2), at<bf16>(L.w3), nullptr);
+                       at<bf16>(L.w1), at<bf16>(L.w2), at<bf16>(L.w3));
     return hip(hipGetLastError(), "weight pack");
   }
 };
@@ -1273,17 +1397,18 @@ olb_status olb_closure_forward_noalloc(int32_t nx, int32_t ny, const float* dev_
   bf16* W1 = reinterpret_cast<bf16*>(sc + NA_W1);
   bf16* W2 = reinterpret_cast<bf16*>(sc + NA_W2);
   bf16* W3 = reinterpret_cast<bf16*>(sc + NA_W3);
-  double* sums = conserve_mask ? reinterpret_cast<double*>(sc + NA_SUMS) : nullptr;
+  double* part4 = conserve_mask ? reinterpret_cast<double*>(sc + NA_PART) : nullptr;
   hipStream_t st = (hipStream_t)hip_stream;
   const int n = 32 * kp_of(4) + 32 * kp_of(32) + 16 * kp_of(32);
-  hipLaunchKernelGGL(pack_weights, dim3((n + 255) / 256), dim3(256), 0, st, dev_params, W1, W2, W3, sums);
+  hipLaunchKernelGGL(pack_weights, dim3((n + 255) / 256), dim3(256), 0, st, dev_params, W1, W2, W3);
   const int tiles_x = (nx + FT - 1) / FT, tiles_y = (ny + FT - 1) / FT, ntiles = tiles_x * tiles_y;
   const int P = nx * ny;
-  hipLaunchKernelGGL(infer_kernel, dim3(infer_grid(ntiles)), dim3(64 * IW), 0, st, dev_moments, nm, W1, W2, W3,
+  const int grid = infer_grid(ntiles);
+  hipLaunchKernelGGL(infer_kernel, dim3(grid), dim3(64 * IW), 0, st, dev_moments, nm, W1, W2, W3,
                      dev_params + 32 * 4 * 9, dev_params + (32 * 4 * 9 + 32) + 32 * 32 * 9, dev_params + (NPARAM - 4),
-                     nx, ny, tiles_x, ntiles, dev_delta, sums);
-  if (sums)
-    hipLaunchKernelGGL(project_kernel, dim3((P + 255) / 256), dim3(256), 0, st, dev_delta, P, nm, sums,
+                     nx, ny, tiles_x, ntiles, dev_delta, part4);
+  if (part4)
+    hipLaunchKernelGGL(project_kernel, dim3((P + 255) / 256), dim3(256), 0, st, dev_delta, P, nm, part4, grid,
                        conserve_mask);
   return hipGetLastError() == hipSuccess ? OLB_OK : OLB_E_DEVICE;
 }

@@ -42,8 +42,20 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16;
 
-__device__ __forceinline__ bf16 to_bf16(float f) {
-  // round to nearest even (finite inputs)
+// FP32 -> bf16, rounded to nearest even: gfx950's conversion instruction
+// (v_cvt_pk_bf16_f32, two values at a time)
+typedef __bf16 bf16x2h __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned to_bf16x2(float lo, float hi) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, bf16x2h));
+}
+__device__ __forceinline__ bf16 to_bf16(float f) { return __builtin_bit_cast(bf16, (__bf16)f); }
+// The same rounding in integer arithmetic, for values converted from an FP64
+// expression: given (__bf16)(float)x the compiler may merge the two
+// conversions into one rounding from FP64 (in some code paths and not in
+// others), which differs where rounding twice does; the network input is
+// defined as rounded to FP32, then to bf16.
+__device__ __forceinline__ bf16 to_bf16_int(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (bf16)(u >> 16);
@@ -457,7 +469,7 @@ __global__ void prep_kernel(const double* __restrict__ m, int P, Norm nm, bf16* 
   if (p >= P) return;
 #pragma unroll
   for (int c = 0; c < 4; ++c)
-    x[(size_t)p * 4 + c] = to_bf16((float)((m[(size_t)c * P + p] - nm.in_mean[c]) * nm.in_inv_scale[c]));
+    x[(size_t)p * 4 + c] = to_bf16_int((float)((m[(size_t)c * P + p] - nm.in_mean[c]) * nm.in_inv_scale[c]));
 }
 
 // MSE loss on the normalised correction, whose target is (reference - m) /
@@ -593,6 +605,9 @@ constexpr int HS = 36;
 constexpr int S0 = R1 + 16, S1 = R2 + 16, S2 = FT + 2;  // row strides of x0, a1, a2 (a2: no wrap, FT = 16)
 // waves per inference workgroup
 constexpr int IW = 8;
+// K steps whose fragments are read ahead in layers 1, 2, 3 (a step of
+// layer 3 is two matrix instructions, of layer 2 six)
+constexpr int PD1 = 1, PD2 = 1, PD3 = 3;
 struct InferLds {
   __attribute__((aligned(16))) bf16 w2[32 * WL];
   bf16 x0[R0 * S0 * 4];
@@ -674,7 +689,7 @@ __device__ __forceinline__ bf16x8 wfrag(const WeightFrags<CIN, COUT>& w, int ks,
 template <int CIN, int COUT>
 __device__ __forceinline__ bf16x8 wfrag(const WeightLds<CIN, COUT>& w, int ks, int t, int lane) { return w.frag(ks, t, lane); }
 
-template <int CIN, int COUT, int R, int IS, int RI, typename Wts, typename Epi>
+template <int CIN, int COUT, int R, int IS, int RI, int PD, typename Wts, typename Epi>
 __device__ __forceinline__ void lds_layer(const bf16* in, const Wts& w, const BiasRegs<COUT>& bias,
                                           int wave, int lane, Epi epi) {
   constexpr int K = 9 * CIN, KP = kp_of(CIN), KS = KP / 32, NT = (COUT + 15) / 16;
@@ -694,10 +709,11 @@ __device__ __forceinline__ void lds_layer(const bf16* in, const Wts& w, const Bi
   for (int m = 0; m < MW; ++m)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
+  // the fragments of K step ks + PD are read before the MFMAs of step ks
+  // (a ring of PD + 1 fragment sets; the scheduling barriers keep that
+  // order), so each step waits for reads issued PD steps earlier
+  auto read_step = [&](int ks, bf16x8* b, bf16x8* a) {
     const int k0 = ks * 32 + 8 * g;
-    bf16x8 b[NT], a[MW];
 #pragma unroll
     for (int t = 0; t < NT; ++t) b[t] = wfrag(w, ks, t, lane);
 #pragma unroll
@@ -708,10 +724,22 @@ __device__ __forceinline__ void lds_layer(const bf16* in, const Wts& w, const Bi
       };
       a[m] = a_frag_sel<CIN>(k0, K, at);
     }
+  };
+  static_assert(PD >= 1, "prefetch depth");
+  bf16x8 b[PD + 1][NT], a[PD + 1][MW];
+#pragma unroll
+  for (int p = 0; p < PD && p < KS; ++p) read_step(p, b[p], a[p]);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int cur = ks % (PD + 1);
+    if (ks + PD < KS) read_step(ks + PD, b[(ks + PD) % (PD + 1)], a[(ks + PD) % (PD + 1)]);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int m = 0; m < MW; ++m)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[t], a[m], acc[m][t], 0, 0, 0);
+      for (int t = 0; t < NT; ++t)
+        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[cur][t], a[cur][m], acc[m][t], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
   }
   // lane (i, g) holds the transposed D[4g + v][i]: channel t*16 + 4g + v of
   // region pixel mt*16 + i
@@ -732,8 +760,9 @@ __device__ __forceinline__ void lds_layer(const bf16* in, const Wts& w, const Bi
 
 // four bf16 values of ReLU(z) as one 8-byte LDS store (dst 8-byte aligned)
 __device__ __forceinline__ void store_relu4(bf16* dst, f32x4 z) {
-  *reinterpret_cast<bf16x4*>(dst) = bf16x4{(short)to_bf16(fmaxf(z[0], 0.f)), (short)to_bf16(fmaxf(z[1], 0.f)),
-                                          (short)to_bf16(fmaxf(z[2], 0.f)), (short)to_bf16(fmaxf(z[3], 0.f))};
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  *reinterpret_cast<u32x2*>(dst) = u32x2{to_bf16x2(fmaxf(z[0], 0.f), fmaxf(z[1], 0.f)),
+                                         to_bf16x2(fmaxf(z[2], 0.f), fmaxf(z[3], 0.f))};
 }
 
 __global__ void __launch_bounds__(64 * IW) infer_kernel(const double* __restrict__ m, Norm nm,
@@ -764,7 +793,7 @@ __global__ void __launch_bounds__(64 * IW) infer_kernel(const double* __restrict
     const int r = tid / R0, c = tid - r * R0;
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch)
-      sm.x0[(r * S0 + c) * 4 + ch] = to_bf16((float)((in[ch] - nm.in_mean[ch]) * nm.in_inv_scale[ch]));
+      sm.x0[(r * S0 + c) * 4 + ch] = to_bf16_int((float)((in[ch] - nm.in_mean[ch]) * nm.in_inv_scale[ch]));
   };
   int tile = blockIdx.x;
   load_input(tile);
@@ -787,7 +816,7 @@ __global__ void __launch_bounds__(64 * IW) infer_kernel(const double* __restrict
     // the input region (and, on the first tile, the weights) are in LDS; a1
     // was last read by the previous tile's layer 2, before its second barrier
     __syncthreads();
-    lds_layer<4, 32, R1, 4, S0>(sm.x0, wf1, bias1, wave, lane, [&](int q, int co, f32x4 z) {
+    lds_layer<4, 32, R1, 4, S0, PD1>(sm.x0, wf1, bias1, wave, lane, [&](int q, int co, f32x4 z) {
       const int r = q / R1, c = q - r * R1;
       store_relu4(sm.a1 + (r * S1 + c) * HS + co, z);
     });
@@ -796,13 +825,13 @@ __global__ void __launch_bounds__(64 * IW) infer_kernel(const double* __restrict
     __syncthreads();
     const int next = tile + gridDim.x;
     if (next < ntiles) load_input(next);
-    lds_layer<32, 32, R2, HS, S1>(sm.a1, wl2, bias2, wave, lane, [&](int q, int co, f32x4 z) {
+    lds_layer<32, 32, R2, HS, S1, PD2>(sm.a1, wl2, bias2, wave, lane, [&](int q, int co, f32x4 z) {
       const int r = q / R2, c = q - r * R2;
       store_relu4(sm.a2 + (r * S2 + c) * HS + co, z);
     });
     if (next < ntiles) store_input();
     __syncthreads();
-    lds_layer<32, 4, FT, HS, S2>(sm.a2, wf3, bias3, wave, lane, [&](int q, int, f32x4 z) {
+    lds_layer<32, 4, FT, HS, S2, PD3>(sm.a2, wf3, bias3, wave, lane, [&](int q, int, f32x4 z) {
       const int r = q / FT, c = q - r * FT;
       const int gy = ty0 + r, gx = tx0 + c;
       if (gy < ny && gx < nx) {

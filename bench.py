@@ -89,6 +89,9 @@ WORKLOADS = {
                 "tau=0.005, dt=5e-4, ds=1/64",
     "spinodal4096": "4096x4096 periodic FP32-mixed spinodal decomposition at T=0.9 T_c, "
                     "n=3.5(1+-1% noise), tau=0.005, dt=2e-4, ds=1/320",
+    "shard4096x512": "one GPU's share of the 4096x4096 FP32-mixed spinodal split into 8 y-strips: rows "
+                     "0..511 of the same field, 4096x512, periodic in y in place of the 3-row halo exchange "
+                     "with the neighbouring strips",
     "channels": "256 walled channels (nx 64..512, ny 128..1024, 43.6 M nodes), FP32-mixed, "
                 "T_w in [0.7, 0.95] T_c, one launch per stage over all channels, graphs of 10 steps",
     "quench": "phase separation between suddenly cooled plates (Sec. 7): 320x640 FP64 (walls across y), "
@@ -129,9 +132,24 @@ def make_cases(workload):
         c.params["precision"] = 1
         c.params["rho_ref"] = I.N_CRIT
         return [c]
+    if workload == "shard4096x512":
+        # the seeded field is drawn row by row, so these are the first 512
+        # rows of the 4096^2 lattice's field
+        c = I.spinodal(4096, 512)
+        c.params["precision"] = 1
+        c.params["rho_ref"] = I.N_CRIT
+        return [c]
     if workload == "channels":
         return I.channels()
     raise SystemExit(f"unknown workload {workload}")
+
+
+def shard_halo_bytes(nx, precision):
+    """Bytes a y-strip shard would receive per RK stage: 3 rows of the 25
+    populations and of the carried (n, Delta p) from each of its two
+    neighbours."""
+    rb = 8 if precision == 0 else 4
+    return 2 * 3 * nx * (25 * rb + 16)
 
 
 def cpu_baseline(workload, min_seconds):
@@ -168,7 +186,7 @@ def cpu_baseline(workload, min_seconds):
     # one thread on a lattice that does not fit in the caches either
     if workload == "wave2048":
         small = I.tile(I.wave64(), 4, 4)
-    elif workload == "spinodal4096":
+    elif workload in ("spinodal4096", "shard4096x512"):
         small = I.spinodal(256, 256)
     else:
         small = I.channel(256, 256, tw=0.8 * I.T_CRIT)
@@ -964,6 +982,9 @@ def main():
     }
     if valu:
         out["roofline"]["valu"] = valu
+    if args.workload == "shard4096x512":
+        out["config"]["halo_bytes_per_stage"] = shard_halo_bytes(cases[0].params["nx"], precision)
+        out["config"]["stage_launch_ms"] = round(avg_launch_s * 1e3, 4)
     print(json.dumps(out))
 
 

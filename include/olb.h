@@ -244,7 +244,8 @@ void olb_batch_free(olb_batch* b);
  * Moment planes are device double [4][ny][nx] (n, u_x, u_y, T), y outer.
  * A closure object holds no device memory of its own: the caller's
  * workspace (256-byte aligned, olb_closure_workspace_bytes) keeps
- * activations, parameters, gradients and Adam state.  Work is enqueued on
+ * activations, parameters, gradients, Adam state and the per-workgroup
+ * partial sums of the reductions over nodes.  Work is enqueued on
  * hip_stream; calls that return host values synchronise it.
  * ------------------------------------------------------------------------ */
 #define OLB_CLOSURE_NPARAM 11588

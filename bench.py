@@ -213,7 +213,7 @@ def cpu_baseline(workload, min_seconds):
 def copy_kernel(gib, reps=10):
     """Device-to-device copy of a known size: calibrates the HBM byte
     counters (FETCH_SIZE / WRITE_SIZE per dispatch) and measures the copy
-    bandwidth this machine sustains."""
+    bandwidth this GPU sustains."""
     import torch
     n = int(gib * (1 << 30)) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda:0")

@@ -188,7 +188,7 @@ def test_fp32_specular_box_density_within_1e5():
 
 
 def test_box_equals_mirror_symmetric_periodic_domain():
-    """The GPU machine against the GPU periodic domain twice as wide started
+    """The specular box on the GPU against the GPU periodic domain twice as wide started
     from fields even about both planes (u_x odd): its left half."""
     olb = _olb()
     c = I.box(70, 21, seed=35, temperature=I.T_CRIT)

@@ -102,6 +102,12 @@ int main() {
   // closure: sizes and null arguments
   expect("closure bytes", olb_closure_workspace_bytes(0, 4, &bytes), OLB_E_ARG);
   expect("closure bytes ok", olb_closure_workspace_bytes(64, 48, &bytes), OLB_OK);
+  // the workspace layout's partial-sum rows at the smallest and the largest
+  // accepted lattices (nx * ny < 2^30), and just past the largest
+  expect("closure bytes 1x1", olb_closure_workspace_bytes(1, 1, &bytes), OLB_OK);
+  expect("closure bytes 5x3", olb_closure_workspace_bytes(5, 3, &bytes), OLB_OK);
+  expect("closure bytes max", olb_closure_workspace_bytes(32768, 32767, &bytes), OLB_OK);
+  expect("closure bytes 2^30", olb_closure_workspace_bytes(32768, 32768, &bytes), OLB_E_ARG);
   olb_closure* cl = nullptr;
   expect("closure small workspace", olb_closure_init(64, 48, small, sizeof small, nullptr, &cl), OLB_E_WORKSPACE);
   expect("closure forward", olb_closure_forward(nullptr, d, d), OLB_E_ARG);

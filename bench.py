@@ -210,10 +210,9 @@ def cpu_baseline(workload, min_seconds):
     return full
 
 
-def copy_kernel(gib, reps=10):
-    """Device-to-device copy of a known size: calibrates the HBM byte
-    counters (FETCH_SIZE / WRITE_SIZE per dispatch) and measures the copy
-    bandwidth this GPU sustains."""
+def copy_gbps(gib, reps=10):
+    """Bandwidth of a plain device-to-device copy of gib GiB (bytes read plus
+    bytes written per second), the best a streaming kernel does on this GPU."""
     import torch
     n = int(gib * (1 << 30)) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda:0")
@@ -227,9 +226,18 @@ def copy_kernel(gib, reps=10):
     e1.record()
     torch.cuda.synchronize()
     secs = e0.elapsed_time(e1) / 1e3 / reps
-    moved = 2 * n * 8
-    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
-                      "copy_GBps": round(moved / secs / 1e9, 1), "reps": reps}))
+    del a, b
+    torch.cuda.empty_cache()
+    return n * 8, 2 * n * 8 / secs / 1e9
+
+
+def copy_kernel(gib, reps=10):
+    """Device-to-device copy of a known size: calibrates the HBM byte
+    counters (FETCH_SIZE / WRITE_SIZE per dispatch) and measures the copy
+    bandwidth this GPU sustains."""
+    nbytes, gbps = copy_gbps(gib, reps)
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                      "copy_GBps": round(gbps, 1), "reps": reps}))
 
 
 def run_quench(args):
@@ -953,6 +961,14 @@ def main():
                 "alu": {"achieved": round(achieved_tflops, 3), "peak": vec_peak, "unit": "TFLOP/s",
                         "frac": round(alu_frac, 4)}}
     lat.close()
+    # a plain copy on the same GPU, after the timed region: the bandwidth a
+    # streaming kernel can reach here, beside the 8 TB/s of the specification
+    _, copy_bw = copy_gbps(1.0, reps=5)
+    roof["copy"] = {"achieved": round(copy_bw, 1), "unit": "GB/s", "what": "1 GiB device-to-device copy, read + write"}
+    roof["frac_of_copy"] = round(achieved_gbs / copy_bw, 4)
+    if traffic:
+        roof["traffic_GBps"] = round(traffic / avg_launch_s / 1e9, 1)
+        roof["traffic_frac_of_copy"] = round(traffic / avg_launch_s / 1e9 / copy_bw, 4)
 
     cpu = None
     if not args.no_cpu:

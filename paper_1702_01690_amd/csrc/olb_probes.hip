@@ -17,7 +17,11 @@
 //                        populations interleaved; workgroups that march up
 //                        2, 4 or 8 tiles of a column and keep the 6 rows that
 //                        consecutive tiles share in LDS; a plain device copy
-//   olb_probes all       both
+//   olb_probes stream    the HBM ceilings a streaming kernel reaches: copy,
+//                        read-only and write-only streams over 2 GiB buffers
+//                        with 16-byte accesses, over several grid sizes; the
+//                        last line gives the best of each
+//   olb_probes all       issue and pattern
 //
 // Every access of the pattern kernels stays inside the arrays it addresses
 // (periodic wrap of rows and columns; buffer resources sized to the array).
@@ -411,16 +415,108 @@ void run_pattern() {
   CK(hipFree(c1));
 }
 
+// ---------------------------------------------------------------------------
+// HBM streaming ceilings
+// ---------------------------------------------------------------------------
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// grid-stride streams of 16-byte elements, U per thread and iteration (all
+// loads of an iteration issued before its stores); NT: non-temporal hints
+template <int U, bool NT>
+__global__ void __launch_bounds__(256) stream_copy(const f32x4* __restrict__ a, f32x4* __restrict__ b, long long n) {
+  const long long step = (long long)gridDim.x * 256 * U;
+  for (long long i = (long long)blockIdx.x * 256 * U + threadIdx.x; i < n; i += step) {
+    f32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long j = i + (long long)u * 256;
+      if (j < n) v[u] = NT ? __builtin_nontemporal_load(a + j) : a[j];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long j = i + (long long)u * 256;
+      if (j < n) {
+        if (NT)
+          __builtin_nontemporal_store(v[u], b + j);
+        else
+          b[j] = v[u];
+      }
+    }
+  }
+}
+template <int U>
+__global__ void __launch_bounds__(256) stream_read(const f32x4* __restrict__ a, float* __restrict__ out, long long n) {
+  const long long step = (long long)gridDim.x * 256 * U;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (long long i = (long long)blockIdx.x * 256 * U + threadIdx.x; i < n; i += step) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long j = i + (long long)u * 256;
+      if (j < n) acc += a[j];
+    }
+  }
+  // the buffer holds zeros: the store never happens, but the loads are kept
+  const float t = acc[0] + acc[1] + acc[2] + acc[3];
+  if (t != 0.f) out[threadIdx.x] = t;
+}
+template <int U>
+__global__ void __launch_bounds__(256) stream_write(f32x4* __restrict__ b, long long n) {
+  const long long step = (long long)gridDim.x * 256 * U;
+  for (long long i = (long long)blockIdx.x * 256 * U + threadIdx.x; i < n; i += step) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long j = i + (long long)u * 256;
+      if (j < n) b[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+}
+
+void run_stream() {
+  const long long bytes = 1LL << 31;
+  const long long n = bytes / 16;
+  f32x4 *a, *b;
+  float* out;
+  CK(hipMalloc(&a, bytes));
+  CK(hipMalloc(&b, bytes));
+  CK(hipMalloc(&out, 256 * sizeof(float)));
+  CK(hipMemset(a, 0, bytes));
+  CK(hipMemset(b, 0, bytes));
+  const int reps = 10;
+  double best_copy = 0, best_read = 0, best_write = 0;
+  auto rep = [&](const char* kind, int blocks, double moved, float ms, double& best) {
+    const double gbps = moved / ms / 1e6;
+    best = gbps > best ? gbps : best;
+    std::printf("{\"probe\":\"stream\",\"kind\":\"%s\",\"blocks\":%d,\"GBps\":%.1f}\n", kind, blocks, gbps);
+    std::fflush(stdout);
+  };
+  for (int blocks : {4096, 8192, 16384}) {
+    rep("copy, non-temporal", blocks, 2.0 * bytes,
+        time_ms([&] { stream_copy<4, true><<<blocks, 256>>>(a, b, n); }, reps), best_copy);
+    rep("copy", blocks, 2.0 * bytes, time_ms([&] { stream_copy<4, false><<<blocks, 256>>>(a, b, n); }, reps),
+        best_copy);
+    rep("read", blocks, 1.0 * bytes, time_ms([&] { stream_read<8><<<blocks, 256>>>(a, out, n); }, reps), best_read);
+    rep("write", blocks, 1.0 * bytes, time_ms([&] { stream_write<8><<<blocks, 256>>>(b, n); }, reps), best_write);
+  }
+  std::printf("{\"probe\":\"stream\",\"best\":{\"copy_GBps\":%.1f,\"read_GBps\":%.1f,\"write_GBps\":%.1f}}\n",
+              best_copy, best_read, best_write);
+  CK(hipFree(a));
+  CK(hipFree(b));
+  CK(hipFree(out));
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
   const char* mode = argc > 1 ? argv[1] : "all";
   const bool all = std::strcmp(mode, "all") == 0;
-  if (!all && std::strcmp(mode, "issue") != 0 && std::strcmp(mode, "pattern") != 0) {
-    std::fprintf(stderr, "usage: olb_probes [issue|pattern|all]\n");
+  if (!all && std::strcmp(mode, "issue") != 0 && std::strcmp(mode, "pattern") != 0 &&
+      std::strcmp(mode, "stream") != 0) {
+    std::fprintf(stderr, "usage: olb_probes [issue|pattern|stream|all]\n");
     return 2;
   }
   if (all || std::strcmp(mode, "issue") == 0) run_issue();
   if (all || std::strcmp(mode, "pattern") == 0) run_pattern();
+  if (std::strcmp(mode, "stream") == 0) run_stream();
   return 0;
 }

@@ -915,7 +915,7 @@ __global__ void apply_kernel(const double* __restrict__ m, const double* __restr
   hfac(uy0, T0 - 1.0, h0y);
   hfac(ux1, T1 - 1.0, h1x);
   hfac(uy1, T1 - 1.0, h1y);
-  const int own = (y + 3) * geo.nx + x;
+  const int own = (y + 3) * (int)geo.rs + x;
 #pragma unroll
   for (int ky = 0; ky < 5; ++ky)
 #pragma unroll

@@ -14,7 +14,11 @@ namespace olbk {
 // fastest.  Interior row y lives at plane row y + 3.
 struct Geometry {
   int nx, ny;
-  int64_t ps;      // plane stride in elements: (ny + 6) * nx
+  // element (k, storage row, x) of a distribution array is at
+  // k * ps + row * rs + x: planes (ps = (ny + 6) nx, rs = nx) or rows of the
+  // 25 populations interleaved (ps = nx, rs = 25 nx)
+  int64_t ps;      // population stride in elements
+  int64_t rs;      // storage-row stride in elements
   int walls;       // 0: periodic y; 1: diffuse walls across y; 2: specular
                    // symmetry plane at the low end, diffuse wall at the high end
 };

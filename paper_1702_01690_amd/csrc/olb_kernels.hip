@@ -9,7 +9,9 @@
 //               reflection walls, or a specular plane at the low end.
 // init / moments / carry / pack / unpack  set-up and read-out.
 //
-// Data layout: f[k][y + 3][x] (see Geometry), one cell per thread.  A 64 x BY
+// Data layout: element (k, y + 3, x) of f at k * ps + (y + 3) * rs + x (see
+// Geometry: planes, or rows of the 25 populations interleaved), one cell per
+// thread.  A 64 x BY
 // thread block covers 64 x BY nodes; lane 63 only provides the left face of
 // its neighbour, so each block writes 63 x BY cells.  Per population, the
 // tile plus a 3-node halo (69 x (BY + 6) values) is staged in LDS; each
@@ -38,15 +40,21 @@ __device__ __forceinline__ gmem<T>* as_global(T* p) {
   return (gmem<T>*)p;
 }
 
-// Buffer resource over one population plane (plane k of an array of planes
-// of plane_bytes each) and loads / stores through it.  A lane's byte offset
-// within a plane is the same for every population, and the plane base sits in
-// scalar registers, so plane accesses cost the vector ALUs no address
-// arithmetic.  Offsets at or past plane_bytes read 0 and write nothing.
+// Buffer resource starting at population k of an array whose populations are
+// pop_bytes apart, with rec_bytes of records (the plane, or everything from
+// population k's first element to the end of the array when the rows of the
+// populations are interleaved), and loads / stores through it.  A lane's byte
+// offset from the population's start is the same for every population, and
+// the base sits in scalar registers, so these accesses cost the vector ALUs no
+// address arithmetic.  Offsets at or past rec_bytes read 0 and write nothing.
 // (Word 3 of the descriptor: raw 32-bit data, the gfx9 buffer format.)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int k, uint32_t pop_bytes,
+                                                            uint32_t rec_bytes) {
+  const char* p = static_cast<const char*>(base) + (int64_t)k * pop_bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), (short)0, (int)rec_bytes, 0x00020000);
+}
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int k, uint32_t plane_bytes) {
-  const char* p = static_cast<const char*>(base) + (int64_t)k * plane_bytes;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), (short)0, (int)plane_bytes, 0x00020000);
+  return plane_rsrc(base, k, plane_bytes, plane_bytes);
 }
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 template <typename Real>
@@ -389,14 +397,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       sy = wrapi(gy, ny);
       my = sy;
     }
-    soff[s] = (sy + 3) * nx + gx;
+    soff[s] = (sy + 3) * (int)a.g.rs + gx;
     moff[s] = my * nx + gx;
   }
   const int oy = WALLS ? min(y, ny + 2) : wrapi(y, ny);
-  const int own = (oy + 3) * nx + wrapi(x, nx);
-  // byte offsets within a plane, for the buffer accesses
+  const int own = (oy + 3) * (int)a.g.rs + wrapi(x, nx);
+  // byte offsets from a population's first element, for the buffer accesses
   constexpr int RB = (int)sizeof(Real);
-  const uint32_t pbytes = (uint32_t)ps * RB;
+  const uint32_t pbytes = (uint32_t)ps * RB, rbytes = (uint32_t)((ny + 5) * a.g.rs + nx) * RB;
   const uint32_t cbytes = (uint32_t)nx * (uint32_t)ny * 8u;
   int soffb[SLOTS], moffb[SLOTS];
 #pragma unroll
@@ -433,7 +441,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   // planes pick the plane per lane: pointer form)
   auto ld_src = [&](int k, int s) -> Real {
     if constexpr (XSPEC) return src[pl_off(k, s)];
-    else return bload<Real>(plane_rsrc(a.fsrc, k, pbytes), soffb[s]);
+    else return bload<Real>(plane_rsrc(a.fsrc, k, pbytes, rbytes), soffb[s]);
   };
   // FN: the stage has an RK base term A f^n (A != 0); a template parameter so
   // that the load counts the waits below rely on are known at compile time
@@ -471,7 +479,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) pre[t % PF][s] = ld_src(tile_pop(t), s);
   // population 12 (p = 0 on both axes) needs no halo: read its own value
-  const Real f12 = XSPEC ? src[12 * ps + own] : bload<Real>(plane_rsrc(a.fsrc, 12, pbytes), ownb);
+  const Real f12 = XSPEC ? src[12 * ps + own] : bload<Real>(plane_rsrc(a.fsrc, 12, pbytes, rbytes), ownb);
 
   auto plane = [&](int t) { return pl0 + (t % NB) * TN; };
 #pragma unroll
@@ -544,7 +552,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   Real fnv[25];
 #pragma unroll
   for (int k = 0; k < 25; ++k)
-    fnv[k] = !use_fn ? (Real)0 : XSPEC ? fnp[k * ps + own] : bload<Real>(plane_rsrc(a.fn, k, pbytes), ownb);
+    fnv[k] = !use_fn ? (Real)0 : XSPEC ? fnp[k * ps + own] : bload<Real>(plane_rsrc(a.fn, k, pbytes, rbytes), ownb);
 
   // stage the second group and refill the ring behind it
 #pragma unroll
@@ -761,7 +769,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       out = acc[k] + (Real)(cfe * (sn * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky]))));
     if (active) {
       if constexpr (XSPEC) dst[k * ps + own] = out;
-      else bstore<Real>(out, plane_rsrc(a.fdst, k, pbytes), ownb);
+      else bstore<Real>(out, plane_rsrc(a.fdst, k, pbytes, rbytes), ownb);
     }
     carry_add(k, (double)out, dn, djx, djy, de);
   }
@@ -868,7 +876,7 @@ __global__ void walls_kernel(const WallBatchArgs wa) {
   const int nx = d.g.nx, ny = d.g.ny;
   if (x >= nx) return;
   Real* __restrict__ f = reinterpret_cast<Real*>(d.f[wa.stage]);
-  const int64_t ps = d.g.ps;
+  const int64_t ps = d.g.ps, rs = d.g.rs;
   // storage rows: interior y -> y + 3
   const int r0 = wall ? ny + 2 : 3, r1 = wall ? ny + 1 : 4, r2 = wall ? ny : 5;
   const int g1 = wall ? ny + 3 : 2, g2 = wall ? ny + 4 : 1, g3 = wall ? ny + 5 : 0;
@@ -892,9 +900,9 @@ __global__ void walls_kernel(const WallBatchArgs wa) {
       const int km = 5 * (4 - k / 5) + k % 5;
       const Real* src = f + km * ps + x;
       Real* pk = f + k * ps + x;
-      pk[g1 * nx] = src[r0 * nx];
-      pk[g2 * nx] = src[r1 * nx];
-      pk[g3 * nx] = src[r2 * nx];
+      pk[g1 * rs] = src[r0 * rs];
+      pk[g2 * rs] = src[r1 * rs];
+      pk[g3 * rs] = src[r2 * rs];
     }
     d.nw[x] = 0.0;
     return;
@@ -911,13 +919,13 @@ __global__ void walls_kernel(const WallBatchArgs wa) {
     for (int kx = 0; kx < 5; ++kx) {
       const int k = 5 * ky + kx;
       Real* pk = f + k * ps + x;
-      const Real v0 = pk[r0 * nx], v1 = pk[r1 * nx], v2 = pk[r2 * nx];
+      const Real v0 = pk[r0 * rs], v1 = pk[r1 * rs], v2 = pk[r2 * rs];
       const Real e1 = (Real)3 * v0 - (Real)3 * v1 + v2;
       const Real e2 = (Real)6 * v0 - (Real)8 * v1 + (Real)3 * v2;
       const Real e3 = (Real)10 * v0 - (Real)15 * v1 + (Real)6 * v2;
-      pk[g1 * nx] = e1;
-      pk[g2 * nx] = e2;
-      pk[g3 * nx] = e3;
+      pk[g1 * rs] = e1;
+      pk[g2 * rs] = e2;
+      pk[g3 * rs] = e3;
       if (ky != 2) {
         // face between the adjacent interior row and the first ghost row;
         // upwind order (far interior ... ghost) is the same at both walls
@@ -950,9 +958,9 @@ __global__ void walls_kernel(const WallBatchArgs wa) {
       double v = nw * (Wk[kx] * (1.0 + hx[kx])) * (Wk[ky] * (1.0 + hy[ky]));
       if (F32) v -= bw[kx] * bw[ky] * rho0;
       Real* pk = f + k * ps + x;
-      pk[g1 * nx] = (Real)v;
-      pk[g2 * nx] = (Real)v;
-      pk[g3 * nx] = (Real)v;
+      pk[g1 * rs] = (Real)v;
+      pk[g2 * rs] = (Real)v;
+      pk[g3 * rs] = (Real)v;
     }
   }
 }
@@ -970,7 +978,7 @@ __global__ void init_kernel(Geometry g, const double* __restrict__ fld, Real* __
   const int m = y * g.nx + x;
   Real fe[25];
   feq25<Real>(fld[m], fld[N + m], fld[2 * N + m], fld[3 * N + m], rho0, tref, fe);
-  const int own = (y + 3) * g.nx + x;
+  const int own = (y + 3) * (int)g.rs + x;
   double n = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
@@ -982,7 +990,7 @@ __global__ void init_kernel(Geometry g, const double* __restrict__ fld, Real* __
 
 template <typename Real>
 __device__ __forceinline__ void load_own(const Geometry& g, const Real* f, int x, int y, Real v[25]) {
-  const int own = (y + 3) * g.nx + x;
+  const int own = (y + 3) * (int)g.rs + x;
 #pragma unroll
   for (int k = 0; k < 25; ++k) v[k] = f[k * g.ps + own];
 }
@@ -1026,7 +1034,7 @@ __global__ void pack_kernel(Geometry g, const Real* __restrict__ f, double* __re
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= g.nx) return;
   const int64_t N = (int64_t)g.nx * g.ny;
-  const int own = (y + 3) * g.nx + x, m = y * g.nx + x;
+  const int own = (y + 3) * (int)g.rs + x, m = y * g.nx + x;
   double h0[5];
   base_h0(tref, h0);
 #pragma unroll
@@ -1044,7 +1052,7 @@ __global__ void unpack_kernel(Geometry g, const double* __restrict__ in, Real* _
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= g.nx) return;
   const int64_t N = (int64_t)g.nx * g.ny;
-  const int own = (y + 3) * g.nx + x, m = y * g.nx + x;
+  const int own = (y + 3) * (int)g.rs + x, m = y * g.nx + x;
   double h0[5];
   base_h0(tref, h0);
 #pragma unroll

@@ -183,6 +183,10 @@ struct Engine {
     ws = (unsigned char*)workspace;
     ws_bytes = bytes;
     rb = p[0].precision == OLB_FP32_MIXED ? 4 : 8;
+    // default tile order: whole rows of tiles with FP64 storage (on the 2048^2
+    // lattice 0.9 % ahead of strips of 8 tile columns), strips of 8 with FP32
+    // storage (0.4 % ahead of whole rows on 4096^2)
+    strip = rb == 8 ? 0 : 8;
     walls = p[0].bc_y != OLB_BC_PERIODIC;
     xspec = p[0].bc_x == OLB_BC_SPECULAR;
     d_desc = (olbk::InstDesc*)ws;
@@ -195,7 +199,18 @@ struct Engine {
       std::memset(&d, 0, sizeof d);
       d.g.nx = p[i].nx;
       d.g.ny = p[i].ny;
-      d.g.ps = (int64_t)(p[i].ny + 6) * p[i].nx;
+      // storage order: the rows of the 25 populations interleaved (element
+      // (k, row, x) at (row * 25 + k) * nx + x) when every byte offset into the
+      // array fits the 32-bit offsets of the buffer accesses, so that a tile's
+      // reads of one row of all populations are one run of addresses; one
+      // plane per population ((k * (ny + 6) + row) * nx + x) for larger arrays
+      if (25 * (int64_t)(p[i].ny + 6) * p[i].nx * rb < ((int64_t)1 << 31)) {
+        d.g.ps = p[i].nx;
+        d.g.rs = 25 * (int64_t)p[i].nx;
+      } else {
+        d.g.ps = (int64_t)(p[i].ny + 6) * p[i].nx;
+        d.g.rs = p[i].nx;
+      }
       d.g.walls = p[i].bc_y;  // 0 periodic, 1 diffuse walls, 2 specular low end + diffuse high wall
       for (int k = 0; k < 3; ++k) d.f[k] = ws + off + k * L.buf;
       d.carry[0] = (double*)(ws + off + 3 * L.buf);

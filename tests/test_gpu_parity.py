@@ -286,6 +286,28 @@ def test_fp64_wave2048_full_size_equals_tiled_crop():
     assert max(err.values()) < TOL64, err
 
 
+def test_fp64_plane_storage_above_2gib_equals_tiled_crop():
+    """A periodic FP64 lattice whose distribution arrays exceed 2^31 bytes
+    (4096 x 2624 nodes: 25 x 2630 x 4096 x 8 B = 2.15 GB each) keeps one plane
+    per population, since interleaved rows would put byte offsets past 32
+    bits; smaller arrays (the 64^2 crop) interleave the populations' rows.
+    Started from a 64^2 noisy vdW field tiled 64 x 41, the large lattice stays
+    equal to the 64^2 run tiled, bitwise: both storage orders give the same
+    bits."""
+    nx, ny = 4096, 2624
+    assert 25 * (ny + 6) * nx * 8 > 2 ** 31 > (ny + 6) * nx * 8
+    crop = I.spinodal(64, 64, steps=10)
+    big = I.spinodal(64, 64, steps=10)
+    big.params.update(nx=nx, ny=ny)
+    fields = tuple(np.tile(a, (ny // 64, nx // 64)) for a in crop.fields)
+    big = I.Case("spinodal4096x2624tiled", big.params, *fields, 10)
+    print(f"[parity] FP64 {nx}x{ny} (plane storage) from a tiled 64^2 field, 10 steps", flush=True)
+    gm, _, _ = run_gpu(big, 10)
+    cm, _, _ = run_gpu(crop, 10)
+    for a, b in zip(gm, cm):
+        np.testing.assert_array_equal(a, np.tile(b, (ny // 64, nx // 64)))
+
+
 @pytest.mark.parametrize("tbase", ["T", None])
 def test_fp32_spinodal4096_full_size_equals_tiled_crop(tbase):
     """The 4096^2 FP32 benchmark configuration (departure storage about

@@ -154,10 +154,12 @@ olb_status olb_set_tile(olb_ctx* c, int32_t by);
  * FP32 rounding).  No effect on FP64 storage.  Synchronous. */
 olb_status olb_set_base_temperature(olb_ctx* c, double T);
 /* Order in which the stage launch visits the tiles: 0 = rows of the tile
- * grid; W > 0 = vertical strips W tiles wide, visited left to right, rows
- * within a strip (tiles that run together then share halos in L2).  Default
- * 8: on a 2048^2 FP64 lattice it reads 25 % fewer bytes than row order.
- * Results do not depend on it (bitwise).  OLB_E_ARG outside 0..1024. */
+ * grid (the reads of a tile row form long runs of consecutive addresses);
+ * W > 0 = vertical strips W tiles wide, visited left to right, rows within a
+ * strip (tiles that run together then share halos in L2: fewer bytes read).
+ * Default: 0 with FP64 storage, 8 with FP32 storage, the faster of the two on
+ * the 2048^2 FP64 and 4096^2 FP32 lattices.  Results do not depend on it
+ * (bitwise).  OLB_E_ARG outside 0..1024. */
 olb_status olb_set_tile_order(olb_ctx* c, int32_t strip);
 
 /* Number of stage-kernel launches olb_step enqueues per RK-3 step (3), and

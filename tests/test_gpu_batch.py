@@ -106,6 +106,34 @@ def test_batch_equals_single_instance_runs_bitwise():
         np.testing.assert_array_equal(bhi, hi)
 
 
+def test_batch_mixing_storage_orders_equals_single_runs_bitwise():
+    """A batch whose instances use different storage orders: the 66 x 45
+    lattice interleaves the rows of its populations, the 4096 x 2624 FP64
+    lattice (25 x 2630 x 4096 x 8 B > 2^31) keeps one plane per population.
+    One launch per stage covers both; each instance's moments equal those of
+    its own single-instance run, bitwise."""
+    olb = _olb()
+    small = I.spinodal(66, 45, seed=21)
+    big = I.spinodal(64, 64, seed=22)
+    nx, ny = 4096, 2624
+    big.params.update(nx=nx, ny=ny)
+    big = I.Case("spinodal4096x2624tiled", big.params,
+                 *(np.tile(a, (ny // 64, nx // 64)) for a in big.fields), 0)
+    assert 25 * (ny + 6) * nx * 8 > 2 ** 31 > 25 * (45 + 6) * 66 * 8
+    cases = [small, big]
+    print("[batch] interleaved 66x45 + planes 4096x2624, FP64, 5 steps", flush=True)
+    b = _batch(cases)
+    b.step(5)
+    b.sync()
+    for i, c in enumerate(cases):
+        lat = olb.Lattice(c.params)
+        lat.set_fields(*c.fields)
+        lat.step(5)
+        for x, y in zip(b.moments(i), lat.moments()):
+            np.testing.assert_array_equal(x, y)
+        del lat
+
+
 @pytest.mark.parametrize("by", [8, 16])
 def test_graph_replays_match_eager_launches(by):
     cases = _channels()

@@ -252,23 +252,39 @@ __device__ __forceinline__ double delta_p(double n, double T, double a, double b
   return nT - nT / (1.0 - b * n) + a * n * n;
 }
 
-// Running moment sums of a node's new populations, in population order; the
-// stage kernel accumulates them as it produces each population, and the set-up
-// kernels use the same sequence so that a restart is bitwise identical.
-__device__ __forceinline__ void carry_add(int k, double v, double& n, double& jx, double& jy,
-                                          double& e) {
-  const double px = Rk[k % 5], py = Rk[k / 5];
-  n += v;
-  jx += px * v;
-  jy += py * v;
-  e += (px * px + py * py) * v;
-}
+// Running moment sums n = sum f, j = sum p f, e = sum |p|^2 f of a node's
+// populations, which must arrive in population order (k = 0..24, row by row
+// of the 5 x 5 set).  The velocity rows share p_y, so a row's values are
+// first added up (r) and n, j_y and the p_y^2 part of e take r once per row;
+// j_x and the p_x^2 part of e take each value with p_x != 0.  That is 72 FP64
+// operations per node instead of 100.  The stage kernel accumulates the sums
+// as it produces each population, and the set-up kernels use the same sequence
+// so that a restart is bitwise identical.
+struct MomSum {
+  double n = 0.0, jx = 0.0, jy = 0.0, e = 0.0, r = 0.0;
+  __device__ __forceinline__ void add(int k, double v) {
+    const int kx = k % 5, ky = k / 5;
+    const double px = Rk[kx], py = Rk[ky];
+    r = kx == 0 ? v : r + v;
+    if (kx != 2) {
+      jx += px * v;
+      e += (px * px) * v;
+    }
+    if (kx == 4) {
+      n += r;
+      if (ky != 2) {
+        jy += py * r;
+        e += (py * py) * r;
+      }
+    }
+  }
+};
 
 // (n, Delta p) of the carry from the running sums.
 template <bool F32>
-__device__ __forceinline__ void carry_finish(double n, double jx, double jy, double e, double rho0,
-                                             double tref, double va, double vb, double& n_out,
-                                             double& dp_out) {
+__device__ __forceinline__ void carry_finish(const MomSum& s, double rho0, double tref, double va,
+                                             double vb, double& n_out, double& dp_out) {
+  double n = s.n, jx = s.jx, jy = s.jy, e = s.e;
   if (F32) {
     n += rho0;
     e += 2.0 * rho0 * tref;
@@ -635,13 +651,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   // registers (ring of PF slots); one barrier per group.  Per population, the
   // contributions that do not need the upper face are accumulated before the
   // barrier, the y-advection after it.
-  double sn = 0.0, sjx = 0.0, sjy = 0.0, se = 0.0;   // moments of f_src
+  MomSum fsum;   // moments of f_src
   const Real tfac = cb;
 
   // everything of population k except its y-advection
   auto local_terms = [&](int k, Real fk) {
     const int kx = k % 5, ky = k / 5;
-    carry_add(k, (double)fk, sn, sjx, sjy, se);
+    fsum.add(k, (double)fk);
     acc[k] += tfac * fk;
     // the force term acts on the whole population: with FP32 storage the
     // base rho0 b_kx b_ky (a uniform value, read through the scalar cache)
@@ -716,16 +732,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     // the kernel and keeps every population's inputs live until then
 #pragma unroll
     for (int i = 0; i < 25; ++i) asm volatile("" : "+v"(acc[i]));
-    asm volatile("" : "+v"(sn), "+v"(sjx), "+v"(sjy), "+v"(se));
+    asm volatile("" : "+v"(fsum.n), "+v"(fsum.jx), "+v"(fsum.jy), "+v"(fsum.e), "+v"(fsum.r));
   }
 
   // moments of f_src, equilibrium (Eqs. feq, g_alpha), RK combine
+  double sn = fsum.n, se = fsum.e;
   if (F32) {
     sn += a.rho0;
     se += 2.0 * a.rho0 * a.tref;
   }
   const double inv_n = 1.0 / sn;
-  const double ux = sjx * inv_n, uy = sjy * inv_n;
+  const double ux = fsum.jx * inv_n, uy = fsum.jy * inv_n;
   const double T = 0.5 * (se * inv_n - ux * ux - uy * uy);
   double hx[5], hy[5];
   hfac(ux, T - 1.0, hx);
@@ -758,7 +775,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       hy_w[i] = w * dyi;
     }
   }
-  double dn = 0.0, djx = 0.0, djy = 0.0, de = 0.0;
+  MomSum dsum;
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
     const int kx = k % 5, ky = k / 5;
@@ -771,12 +788,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       if constexpr (XSPEC) dst[k * ps + own] = out;
       else bstore<Real>(out, plane_rsrc(a.fdst, k, pbytes, rbytes), ownb);
     }
-    carry_add(k, (double)out, dn, djx, djy, de);
+    dsum.add(k, (double)out);
   }
 
   if (active) {
     double cn, cdp;
-    carry_finish<F32>(dn, djx, djy, de, a.rho0, a.tref, a.a, a.b, cn, cdp);
+    carry_finish<F32>(dsum, a.rho0, a.tref, a.a, a.b, cn, cdp);
     const int64_t N = (int64_t)nx * ny;
     const int m = y * nx + x;
     if constexpr (XSPEC) {
@@ -979,13 +996,13 @@ __global__ void init_kernel(Geometry g, const double* __restrict__ fld, Real* __
   Real fe[25];
   feq25<Real>(fld[m], fld[N + m], fld[2 * N + m], fld[3 * N + m], rho0, tref, fe);
   const int own = (y + 3) * (int)g.rs + x;
-  double n = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+  MomSum sum;
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
     f[k * g.ps + own] = fe[k];
-    carry_add(k, (double)fe[k], n, jx, jy, e);
+    sum.add(k, (double)fe[k]);
   }
-  carry_finish<std::is_same<Real, float>::value>(n, jx, jy, e, rho0, tref, va, vb, carry[m], carry[N + m]);
+  carry_finish<std::is_same<Real, float>::value>(sum, rho0, tref, va, vb, carry[m], carry[N + m]);
 }
 
 template <typename Real>
@@ -1020,12 +1037,12 @@ __global__ void carry_kernel(Geometry g, const Real* __restrict__ f, double* __r
   if (x >= g.nx) return;
   Real v[25];
   load_own(g, f, x, y, v);
-  double n = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+  MomSum sum;
 #pragma unroll
-  for (int k = 0; k < 25; ++k) carry_add(k, (double)v[k], n, jx, jy, e);
+  for (int k = 0; k < 25; ++k) sum.add(k, (double)v[k]);
   const int64_t N = (int64_t)g.nx * g.ny;
   const int m = y * g.nx + x;
-  carry_finish<std::is_same<Real, float>::value>(n, jx, jy, e, rho0, tref, va, vb, carry[m], carry[N + m]);
+  carry_finish<std::is_same<Real, float>::value>(sum, rho0, tref, va, vb, carry[m], carry[N + m]);
 }
 
 template <typename Real>

@@ -137,13 +137,13 @@ __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, doub
 }
 
 // FP32: the weights are products of squared indicators (eighth powers of the
-// differences), which would leave the FP32 range, so the indicators are
-// scaled by 2^-e, with 2^e bounding the largest of them (m = f 2^e,
-// 1/2 <= f < 1): the scaled indicators lie in [0, 1) and the largest in
-// [1/2, 1).  The scaling is exact and cancels in the weights; the candidate
-// offsets stay unscaled.  An indicator that underflows acts as a vanishing
-// one, which changes the result by far less than FP32 rounding (its three
-// values then agree to far below the rounding of f_i).
+// differences), which would leave the FP32 range, so the three indicators are
+// multiplied by one factor c close to 1/m, m the largest of them: the scaled
+// indicators lie in [0, 1) and the largest in [1/2, 9/16].  A common factor
+// cancels in the weights (it only adds a rounding to each scaled indicator);
+// the candidate offsets stay unscaled.  An indicator that underflows acts as a
+// vanishing one, which changes the result by far less than FP32 rounding (its
+// three values then agree to far below the rounding of f_i).
 //
 // Instruction forms (gfx950 issues two FP32 add / mul / FMA instructions per
 // SIMD quad-cycle when no operand sits in a scalar register, and one
@@ -151,14 +151,15 @@ __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, doub
 // formed with the opposite sign (e1 = -d1, e4 = -d4), so that 3 d2 - d1 and
 // 3 d3 - d4 are FMAs with a literal and no negated operand (3.0 is not an
 // inline constant, and the negated form would take it from a scalar
-// register); a3 enters squared only, so its sign is free.  The scale 2^-e is
-// assembled from the exponent field of the largest indicator by integer
-// arithmetic and applied by multiplication: for a normal m with biased
-// exponent E, m in [2^(E-127), 2^(E-126)), the factor 2^(126-E) puts m in
-// [1/2, 1).  Flipping signs and scaling by a power of two are exact, so the
-// result is the same as with d1, d4 and frexp / ldexp.  (m below the normal
-// range, i.e. differences of order 1e-19, is scaled by 2^126 only; the
-// weights are then those of values that agree far below FP32 rounding.)
+// register); a3 enters squared only, so its sign is free.  The factor c is
+// one integer subtraction from the bits of m: for a normal m = (1 + u) 2^(E-127)
+// (biased exponent E, mantissa fraction u), the bits 0x7e800000 - bits(m)
+// encode c = (2 - u) 2^(125-E), so that c m = (2 - u)(1 + u) / 4 lies in
+// [1/2, 9/16]; no frexp / ldexp, and no mask of the exponent field.
+// (m below the normal range, i.e. differences of order 1e-19, gets c close to
+// 2^126; the weights are then those of values that agree far below FP32
+// rounding.  m = 0 happens only with d2 = d3 = 0 and e1 = e4 = 0, when every
+// candidate offset vanishes.)
 __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3, float v4) {
   const float e1 = v0 - v1, d2 = v2 - v1, d3 = v3 - v2, e4 = v3 - v4;
   const float a1 = d2 + e1, b1 = __builtin_fmaf(3.0f, d2, e1);
@@ -168,7 +169,7 @@ __device__ __forceinline__ float weno_rec(float v0, float v1, float v2, float v3
   const float t2 = __builtin_fmaf(a2 * (13.0f / 3.0f), a2, b2 * b2);
   const float t3 = __builtin_fmaf(a3 * (13.0f / 3.0f), a3, b3 * b3);
   const float m = fmaxf(fmaxf(t1, t2), t3);
-  const float sc = __uint_as_float(0x7e800000u - (__float_as_uint(m) & 0x7f800000u));
+  const float sc = __uint_as_float(0x7e800000u - __float_as_uint(m));
   const float s1 = t1 * sc, s2 = t2 * sc, s3 = t3 * sc;
   const float q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
   // 2^-126 in the second weight keeps den > 0 without a branch: den would

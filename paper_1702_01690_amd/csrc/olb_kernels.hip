@@ -313,16 +313,24 @@ __device__ __forceinline__ void carry_finish(const MomSum& s, double rho0, doubl
 template <typename Real>
 constexpr int pop_group() { return std::is_same<Real, float>::value ? OLB_GROUP32 : OLB_GROUP64; }
 
+// FP32 stage: the population planes sit side by side in LDS rows whose pitch
+// is a multiple of 64 values (planes 128 values apart), so that the reads six
+// rows apart of a y-face reconstruction take the 64-value offset unit of the
+// paired LDS reads, and every read of every plane takes its offset from one
+// of two base registers as an immediate (no address arithmetic per read).
+// FP64 stage: planes one after another, rows of 69 values (the FP64 stage
+// has no registers to spare for the two bases).
 template <typename Real, int BY>
 struct StageLds {
+  static constexpr bool WIDE = std::is_same<Real, float>::value;
   static constexpr int TW = 69;          // tile columns x0-3 .. x0+65
   static constexpr int TH = BY + 6;      // tile rows    y0-3 .. y0+BY+2
-  static constexpr int TN = TW * TH;
-  static constexpr int PB = TN * (int)sizeof(Real);
-  static constexpr int MB = TN * (int)sizeof(double);
+  static constexpr int TN = TW * TH;     // values per plane
   static constexpr int G = pop_group<Real>();
+  static constexpr int PR = WIDE ? 2 * G * 128 : TW;   // row pitch of the planes
+  static constexpr int PO = WIDE ? 128 : TN;           // offset from one plane to the next
   // 2G population planes
-  __attribute__((aligned(16))) Real buf[2 * G * TN];
+  __attribute__((aligned(16))) Real buf[WIDE ? TH * PR : 2 * G * TN];
   // the carried (n, Delta p) tile, apart from the planes: the first group of
   // populations is reconstructed while it is still on its way
   __attribute__((aligned(16))) double cm[2 * TN];
@@ -363,7 +371,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
                                            StageLds<Real, BY>& sm) {
   constexpr bool F32 = std::is_same<Real, float>::value;
   constexpr int TW = StageLds<Real, BY>::TW;
+  constexpr int TH = StageLds<Real, BY>::TH;
   constexpr int TN = StageLds<Real, BY>::TN;
+  constexpr int PO = StageLds<Real, BY>::PO;
+  constexpr int PR = StageLds<Real, BY>::PR;
   constexpr int NT = 64 * BY;
   constexpr int SLOTS = (TN + NT - 1) / NT;
   Real* const pl0 = sm.buf;
@@ -388,12 +399,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   // reversed x velocity (xfl), and the carried fields of the mirror column.
   // In a wall's ghost rows this reflects the wall ghosts once more (corners).
   int soff[SLOTS], moff[SLOTS];
+  // LDS places of the slots in a plane (add the plane's offset)
+  int lpo[SLOTS];
   bool xfl[SLOTS];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int i = tid + s * NT;
     const int ii = i < TN ? i : TN - 1;
     const int rr = ii / TW, cc = ii - rr * TW;
+    lpo[s] = StageLds<Real, BY>::WIDE ? rr * PR + cc : i;
     int gx;
     xfl[s] = false;
     if (XSPEC) {
@@ -498,19 +512,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   // population 12 (p = 0 on both axes) needs no halo: read its own value
   const Real f12 = XSPEC ? src[12 * ps + own] : bload<Real>(plane_rsrc(a.fsrc, 12, pbytes, rbytes), ownb);
 
-  auto plane = [&](int t) { return pl0 + (t % NB) * TN; };
+  auto plane = [&](int t) { return pl0 + (t % NB) * PO; };
 #pragma unroll
   for (int j = 0; j < G; ++j)
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int i = tid + s * NT;
-      if (i < TN) plane(j)[i] = pre0[j][s];
+      if (i < TN) plane(j)[lpo[s]] = pre0[j][s];
     }
   __syncthreads();
 
-  const int rowc = (ty + 3) * TW + tx;   // x-face row values start here
-  const int colc = ty * TW + tx + 3;     // y-face column values start here
-  const int ownc = (ty + 3) * TW + tx + 3;
+  // x-face row values and y-face column values start at these places (FP32:
+  // held in registers as they are, so that every read of a plane takes its
+  // offset as an immediate)
+  int rowc = (ty + 3) * PR + tx;
+  int colc = ty * PR + tx + 3;
+  if (F32) asm volatile("" : "+v"(rowc), "+v"(colc));
+  const int ownc = rowc + 3;
 
   // WENO face reconstructions of population slot t from its plane: the left
   // x face (its right neighbour's arrives by a lane shift) and the lower y
@@ -529,9 +547,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     if (ky != 2 && ty == t % BY) {
       __builtin_amdgcn_s_setprio(2);
       __builtin_amdgcn_sched_barrier(0);
-      const int ct = BY * TW + tx + 3;
-      const Real d0 = P[ct], d1 = P[ct + TW], d2 = P[ct + 2 * TW], d3 = P[ct + 3 * TW],
-                 d4 = P[ct + 4 * TW], d5 = P[ct + 5 * TW];
+      const int ct = BY * PR + tx + 3;
+      const Real d0 = P[ct], d1 = P[ct + PR], d2 = P[ct + 2 * PR], d3 = P[ct + 3 * PR],
+                 d4 = P[ct + 4 * PR], d5 = P[ct + 5 * PR];
       fy_sh[t % NB][BY][tx] = py > 0.0 ? weno_rec(d0, d1, d2, d3, d4) : weno_rec(d5, d4, d3, d2, d1);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -544,8 +562,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       rxl = px > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
     }
     if (ky != 2) {
-      const Real c0 = P[colc], c1 = P[colc + TW], c2 = P[colc + 2 * TW], c3 = P[colc + 3 * TW],
-                 c4 = P[colc + 4 * TW], c5 = P[colc + 5 * TW];
+      const Real c0 = P[colc], c1 = P[colc + PR], c2 = P[colc + 2 * PR], c3 = P[colc + 3 * PR],
+                 c4 = P[colc + 4 * PR], c5 = P[colc + 5 * PR];
       ryl = py > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
       fy_sh[t % NB][ty][tx] = ryl;
     }
@@ -578,7 +596,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       const int i = tid + s * NT;
-      if (i < TN) plane(t)[i] = pre[t % PF][s];
+      if (i < TN) plane(t)[lpo[s]] = pre[t % PF][s];
     }
     if (t + PF < 24) {
 #pragma unroll
@@ -712,7 +730,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           const int i = tid + s * NT;
-          if (i < TN) plane(t)[i] = pre[t % PF][s];
+          if (i < TN) plane(t)[lpo[s]] = pre[t % PF][s];
         }
         if (t + PF < 24) {
 #pragma unroll

@@ -37,6 +37,7 @@ struct StageArgs {
   double rho0;          // FP32 departure base: f = rho0 b_kx b_ky + stored value,
   double tref;          // b = w (1 + h(0, tref - 1)) per axis (tref = 1: b = w)
   const float* base;    // [25] rho0 b_kx b_ky (FP32 storage), in the instance descriptor
+  double wguard;        // BatchArgs::wguard
 };
 
 // One lattice instance of a batch (device table, ascending tile_base).
@@ -62,6 +63,8 @@ struct BatchArgs {
   int strip;            // tile order: 0 = rows of the tile grid; W > 0 = strips
                         // W tiles wide, rows within a strip, strips left to right
   double A, B;          // f_dst = A f^n + B (f_src + dt L[f_src])
+  double wguard;        // 2^-1000: keeps the FP64 WENO denominator positive (an
+                        // argument, so that it stays in scalar registers)
 };
 
 struct WallBatchArgs {

@@ -114,7 +114,8 @@ __device__ __forceinline__ float frcp(float d) { return __builtin_amdgcn_rcpf(d)
 // and the ideal weights and the 1/6 are folded into them: with
 // W1 = (s2 s3)^2, W2 = (s1 s3)^2, W3 = (s1 s2)^2 the face value is
 //   f_i + [W1 e1/6 + W2 e2 + W3 e3/2] / [W1 + 6 W2 + 3 W3].
-__device__ __forceinline__ double weno_rec(double v0, double v1, double v2, double v3, double v4) {
+__device__ __forceinline__ double weno_rec(double v0, double v1, double v2, double v3, double v4,
+                                           double guard = 0x1p-1000) {
   const double d1 = v1 - v0, d2 = v2 - v1, d3 = v3 - v2, d4 = v4 - v3;
   const double a1 = d2 - d1, b1 = __builtin_fma(3.0, d2, -d1);
   const double a2 = d3 - d2, b2 = d2 + d3;
@@ -123,11 +124,14 @@ __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, doub
   const double s2 = __builtin_fma(a2 * (13.0 / 3.0), a2, b2 * b2);
   const double s3 = __builtin_fma(a3 * (13.0 / 3.0), a3, b3 * b3);
   const double q1 = s1 * s1, q2 = s2 * s2, q3 = s3 * s3;
-  // 2^-1000 in the second weight keeps den > 0 without a branch (the FP32
-  // form below explains why the result is then f_i when two indicators
-  // vanish); a weight it could disturb would need differences of 1e-36,
-  // far below the rounding of any population value
-  const double w1 = q2 * q3, w2 = __builtin_fma(q1, q3, 0x1p-1000), w3 = q1 * q2;
+  // guard = 2^-1000 in the second weight keeps den > 0 without a branch (the
+  // FP32 form below explains why the result is then f_i when two indicators
+  // vanish); a weight it could disturb would need differences of 1e-36, far
+  // below the rounding of any population value.  The stage kernel passes it
+  // from a kernel argument: FP64 constants have no literal form in the
+  // three-operand FMA, and a constant addend is otherwise rebuilt in vector
+  // registers (two moves) for every face.
+  const double w1 = q2 * q3, w2 = __builtin_fma(q1, q3, guard), w3 = q1 * q2;
   const double g1 = __builtin_fma(5.0 / 6.0, d2, d1 * (-1.0 / 3.0));
   const double g2 = __builtin_fma(2.0, d3, d2);
   const double g3 = __builtin_fma(2.0, d3, d4 * -0.5);
@@ -530,6 +534,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   if (F32) asm volatile("" : "+v"(rowc), "+v"(colc));
   const int ownc = rowc + 3;
 
+  // one WENO-5 face value (FP64: with the denominator guard from the arguments)
+  auto wrec = [&](Real v0, Real v1, Real v2, Real v3, Real v4) -> Real {
+    if constexpr (F32) return weno_rec(v0, v1, v2, v3, v4);
+    else return weno_rec(v0, v1, v2, v3, v4, a.wguard);
+  };
+
   // WENO face reconstructions of population slot t from its plane: the left
   // x face (its right neighbour's arrives by a lane shift) and the lower y
   // face (published in fy_sh for the wave below); returns the x advection
@@ -550,7 +560,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
       const int ct = BY * PR + tx + 3;
       const Real d0 = P[ct], d1 = P[ct + PR], d2 = P[ct + 2 * PR], d3 = P[ct + 3 * PR],
                  d4 = P[ct + 4 * PR], d5 = P[ct + 5 * PR];
-      fy_sh[t % NB][BY][tx] = py > 0.0 ? weno_rec(d0, d1, d2, d3, d4) : weno_rec(d5, d4, d3, d2, d1);
+      fy_sh[t % NB][BY][tx] = py > 0.0 ? wrec(d0, d1, d2, d3, d4) : wrec(d5, d4, d3, d2, d1);
       __builtin_amdgcn_sched_barrier(0);
     }
     fk = P[ownc];
@@ -559,12 +569,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     if (kx != 2) {
       const Real c0 = P[rowc], c1 = P[rowc + 1], c2 = P[rowc + 2], c3 = P[rowc + 3],
                  c4 = P[rowc + 4], c5 = P[rowc + 5];
-      rxl = px > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
+      rxl = px > 0.0 ? wrec(c0, c1, c2, c3, c4) : wrec(c5, c4, c3, c2, c1);
     }
     if (ky != 2) {
       const Real c0 = P[colc], c1 = P[colc + PR], c2 = P[colc + 2 * PR], c3 = P[colc + 3 * PR],
                  c4 = P[colc + 4 * PR], c5 = P[colc + 5 * PR];
-      ryl = py > 0.0 ? weno_rec(c0, c1, c2, c3, c4) : weno_rec(c5, c4, c3, c2, c1);
+      ryl = py > 0.0 ? wrec(c0, c1, c2, c3, c4) : wrec(c5, c4, c3, c2, c1);
       fy_sh[t % NB][ty][tx] = ryl;
     }
     if (ky != 2 && ty == t % BY) __builtin_amdgcn_s_setprio(0);
@@ -873,6 +883,7 @@ __global__ void __launch_bounds__(64 * BY, min_waves_per_simd<Real>()) stage_ker
   a.rho0 = d.rho0;
   a.tref = d.tref;
   a.base = d.base;
+  a.wguard = ba.wguard;
   const int local = t - d.tile_base;
   int tile_x, tile_y;
   if (ba.strip > 0 && ba.strip < d.tiles_x) {

@@ -438,6 +438,7 @@ struct Engine {
       ba.strip = strip;
       ba.A = olbc::RK_A[s];
       ba.B = olbc::RK_B[s];
+      ba.wguard = 0x1p-1000;
       olb_status e = hip(olbk::launch_stage(ba, rb, by, walls, xspec, stream), "stage kernel");
       if (e) return e;
       cur ^= 1;

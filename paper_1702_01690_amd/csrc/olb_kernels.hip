@@ -317,16 +317,21 @@ __device__ __forceinline__ void carry_finish(const MomSum& s, double rho0, doubl
 template <typename Real>
 constexpr int pop_group() { return std::is_same<Real, float>::value ? OLB_GROUP32 : OLB_GROUP64; }
 
-// FP32 stage: the population planes sit side by side in LDS rows whose pitch
-// is a multiple of 64 values (planes 128 values apart), so that the reads six
-// rows apart of a y-face reconstruction take the 64-value offset unit of the
+// Wide layout (FP32 stage, 63 x 8 and 63 x 16 tiles, no specular x planes):
+// the population planes sit side by side in LDS rows whose pitch is a
+// multiple of 64 values (planes 128 values apart), so that the reads six rows
+// apart of a y-face reconstruction take the 64-value offset unit of the
 // paired LDS reads, and every read of every plane takes its offset from one
 // of two base registers as an immediate (no address arithmetic per read).
-// FP64 stage: planes one after another, rows of 69 values (the FP64 stage
-// has no registers to spare for the two bases).
-template <typename Real, int BY>
+// Otherwise planes one after another, rows of 69 values: the FP64 stage has
+// no registers to spare for the two bases, and the FP32 specular-x and
+// 63 x 12 variants would spill with them.
+template <typename Real, int BY, bool XSPEC>
+constexpr bool wide_lds() { return std::is_same<Real, float>::value && !XSPEC && BY != 12; }
+
+template <typename Real, int BY, bool WIDE_>
 struct StageLds {
-  static constexpr bool WIDE = std::is_same<Real, float>::value;
+  static constexpr bool WIDE = WIDE_;
   static constexpr int TW = 69;          // tile columns x0-3 .. x0+65
   static constexpr int TH = BY + 6;      // tile rows    y0-3 .. y0+BY+2
   static constexpr int TN = TW * TH;     // values per plane
@@ -372,13 +377,14 @@ constexpr int prefetch_depth() { return std::is_same<Real, float>::value ? OLB_P
 
 template <typename Real, int BY, bool WALLS, bool FN, bool XSPEC>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, const int y0,
-                                           StageLds<Real, BY>& sm) {
+                                           StageLds<Real, BY, wide_lds<Real, BY, XSPEC>()>& sm) {
   constexpr bool F32 = std::is_same<Real, float>::value;
-  constexpr int TW = StageLds<Real, BY>::TW;
-  constexpr int TH = StageLds<Real, BY>::TH;
-  constexpr int TN = StageLds<Real, BY>::TN;
-  constexpr int PO = StageLds<Real, BY>::PO;
-  constexpr int PR = StageLds<Real, BY>::PR;
+  using SL = StageLds<Real, BY, wide_lds<Real, BY, XSPEC>()>;
+  constexpr int TW = SL::TW;
+  constexpr int TH = SL::TH;
+  constexpr int TN = SL::TN;
+  constexpr int PO = SL::PO;
+  constexpr int PR = SL::PR;
   constexpr int NT = 64 * BY;
   constexpr int SLOTS = (TN + NT - 1) / NT;
   Real* const pl0 = sm.buf;
@@ -411,7 +417,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     const int i = tid + s * NT;
     const int ii = i < TN ? i : TN - 1;
     const int rr = ii / TW, cc = ii - rr * TW;
-    lpo[s] = StageLds<Real, BY>::WIDE ? rr * PR + cc : i;
+    lpo[s] = SL::WIDE ? rr * PR + cc : i;
     int gx;
     xfl[s] = false;
     if (XSPEC) {
@@ -526,12 +532,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
     }
   __syncthreads();
 
-  // x-face row values and y-face column values start at these places (FP32:
-  // held in registers as they are, so that every read of a plane takes its
-  // offset as an immediate)
+  // x-face row values and y-face column values start at these places (wide
+  // layout: held in registers as they are, so that every read of a plane
+  // takes its offset as an immediate)
   int rowc = (ty + 3) * PR + tx;
   int colc = ty * PR + tx + 3;
-  if (F32) asm volatile("" : "+v"(rowc), "+v"(colc));
+  if (SL::WIDE) asm volatile("" : "+v"(rowc), "+v"(colc));
   const int ownc = rowc + 3;
 
   // one WENO-5 face value (FP64: with the denominator guard from the arguments)
@@ -856,7 +862,7 @@ __device__ __forceinline__ int find_instance(const InstDesc* inst, int ninst, in
 // neighbour starts about half a tile lifetime later and misses them).
 template <typename Real, int BY, bool WALLS, bool FN, bool XSPEC>
 __global__ void __launch_bounds__(64 * BY, min_waves_per_simd<Real>()) stage_kernel(const BatchArgs ba) {
-  __shared__ StageLds<Real, BY> sm;
+  __shared__ StageLds<Real, BY, wide_lds<Real, BY, XSPEC>()> sm;
   const int bid = blockIdx.x;
   const int q8 = ba.total_tiles >> 3, r8 = ba.total_tiles & 7, xcd = bid & 7;
   const int t = xcd * q8 + (xcd < r8 ? xcd : r8) + (bid >> 3);

@@ -467,6 +467,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int x0, con
   gmem<double>* cout = as_global(a.cout);
 
   constexpr int G = pop_group<Real>();
+  static_assert(12 % G == 0, "population 12 must start a group: the moment sums take the populations in order");
   constexpr int NB = 2 * G;
   constexpr int PF = prefetch_depth<Real>() - 1;
   static_assert(PF >= G, "the register ring must hold the next group");

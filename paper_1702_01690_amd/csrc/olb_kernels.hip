@@ -159,7 +159,9 @@ __device__ __forceinline__ double weno_rec(double v0, double v1, double v2, doub
 // one integer subtraction from the bits of m: for a normal m = (1 + u) 2^(E-127)
 // (biased exponent E, mantissa fraction u), the bits 0x7e800000 - bits(m)
 // encode c = (2 - u) 2^(125-E), so that c m = (2 - u)(1 + u) / 4 lies in
-// [1/2, 9/16]; no frexp / ldexp, and no mask of the exponent field.
+// [1/2, 9/16]; no frexp / ldexp, and no mask of the exponent field.  This
+// holds for m < 2^125, i.e. for differences below about 1e18, far beyond any
+// population value (from 2^125 on, c falls below the normal range).
 // (m below the normal range, i.e. differences of order 1e-19, gets c close to
 // 2^126; the weights are then those of values that agree far below FP32
 // rounding.  m = 0 happens only with d2 = d3 = 0 and e1 = e4 = 0, when every
